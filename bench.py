@@ -1,0 +1,159 @@
+"""Benchmark: path-steps/s for price + full vol-grid adjoint on one MI355X.
+
+A step is one pass of the whole path over one batch: Philox normals, LDS vol
+lookup, log-Euler stepping with stored states, payoff and FP64 reductions, the
+reverse sweep with the fixed-point LDS gradient histogram, and the fixed-order
+merge -- for the workload of the paper's timing run: one call, 2^19 paths
+(the paper's 500K), 156 weekly steps, a 60 x 30 = 1800-node grid, FP32 stepping.
+
+Prints one JSON line.  Also reports the FP64 GPU variant, the forward-only and
+checkpointed variants, their accuracy against each other, the roofline of the
+dominant kernel and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X public peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3          # FP32 vector
+PEAK_VALU_TOPS = PEAK_FP32_TFLOPS / 2.0   # 256 CUs x 128 FP32 lanes/clk x 2.4 GHz (lane-ops/s)
+
+# Algorithmic work per path-step ("Roofline"): VALU lane-operations
+# of the method's arithmetic, and HBM bytes of the stored states.
+OPS_FWD = 34.0      # Philox/4 (15) + uniforms (3) + Box-Muller (4) + lookup (9) + Euler (2) + store (1)
+OPS_REV = 30.0      # load (1) + lookup (9) + dy/dsigma (3) + adjoint (5) + fixed-point scatter (12)
+BYTES_FWD = 4.0     # one FP32 state written per path-step
+BYTES_REV = 4.0     # one FP32 state read per path-step
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP64/forward/checkpoint variants")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); "
+              "the path shards by Philox path range, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2002_02481_amd as lv
+    import workloads as W
+
+    wl = W.single_call_60x30()
+    s = wl.surface
+    P, N = wl.n_paths, wl.n_steps
+    dev = torch.device("cuda:0")
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device=dev)
+    ctx = lv.Context(0)
+    kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, ctx=ctx)
+    strikes, mats = wl.book.strike, wl.book.maturity
+
+    def run(out=None, **opts):
+        return lv.price_and_grad_dev(sig, 100.0, strikes, mats, P, N, wl.seed, out=out, **kw, **opts)
+
+    out = [t for t in run()]
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        run(out=out, profile=True)
+    torch.cuda.synchronize()
+    ctx.kernel_times(reset=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run(out=out, profile=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = P * N / (ms_per_step * 1e-3)
+    times = ctx.kernel_times(reset=True)
+    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in times.items()}
+
+    # roofline of the dominant kernel
+    dom = max(("fwd", "rev"), key=lambda k: avg[k])
+    units = P * N
+    ops = (OPS_FWD if dom == "fwd" else OPS_REV) * units
+    byts = (BYTES_FWD if dom == "fwd" else BYTES_REV) * units
+    achieved_tops = ops / (avg[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved_tops, 3),
+                "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "frac": round(achieved_tops / PEAK_VALU_TOPS, 4),
+                "traffic": None,
+                "hbm_achieved_GBs": round(byts / (avg[dom] * 1e-3) / 1e9, 1),
+                "avg_ms": {k: round(v, 5) for k, v in avg.items() if v}}
+
+    price32, se32, grad32, delta32 = [t.cpu().numpy().copy() for t in out]
+    result = {
+        "metric": "path-steps/s for price + full vol-grid adjoint, FP32 vs FP64 GPU at fixed error",
+        "value": value, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded 60x30 local-vol surface, Philox streams)",
+        "config": {"workload": wl.name, "paths": P, "steps": N, "grid": list(s.sigma.shape),
+                   "options": 1, "adjoint": "stored", "parallelism": "none"},
+        "roofline": roofline,
+    }
+
+    if not args.no_variants:
+        variants = {}
+        def timed(n, **opts):
+            o = [t for t in run(**opts)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                run(out=o, **opts)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / n, o
+        ms64, o64 = timed(max(3, args.steps // 4), precision=64)
+        p64, g64 = o64[0].cpu().numpy(), o64[2].cpu().numpy()
+        variants["fp64_gpu"] = {"ms_per_step": ms64, "value": P * N / (ms64 * 1e-3)}
+        msf, _ = timed(args.steps, adjoint="none", want_grad=False)
+        variants["fp32_forward_only"] = {"ms_per_step": msf, "value": P * N / (msf * 1e-3)}
+        msc, oc = timed(max(3, args.steps // 2), adjoint="checkpoint")
+        variants["fp32_checkpoint"] = {"ms_per_step": msc, "value": P * N / (msc * 1e-3),
+                                       "max_bucket_err_vs_stored": float(np.abs(oc[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
+        result["variants"] = variants
+        result["accuracy"] = {
+            "fp32_vs_fp64_gpu_price_abs": float(abs(price32[0] - p64[0])),
+            "fp32_vs_fp64_gpu_max_bucket_err_rel_maxg": float(np.abs(grad32 - g64).max() / np.abs(g64).max()),
+            "price": float(price32[0]), "stderr": float(se32[0]),
+        }
+
+    if not args.no_cpu:
+        import oracle
+        o = oracle.default()
+        n_threads = oracle.default_threads()
+        sample = 32768
+        t0 = time.perf_counter()
+        o.price_and_grad(s, wl.book, sample, N, wl.seed, n_threads=n_threads)
+        dt = time.perf_counter() - t0
+        # scale the sample up to a budget of about 10 s of CPU work
+        reps = max(1, int(10.0 / max(dt, 1e-3)))
+        if reps > 1:
+            t0 = time.perf_counter()
+            o.price_and_grad(s, wl.book, sample * reps, N, wl.seed, n_threads=n_threads)
+            dt = time.perf_counter() - t0
+            sample *= reps
+        result["cpu_baseline"] = {"value": sample * N / dt, "unit": "path-steps/s", "cores": n_threads,
+                                  "kind": "oracle",
+                                  "sample": f"{sample} paths x {N} steps of {wl.name}, FP64, price + grid adjoint"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

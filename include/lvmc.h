@@ -1,0 +1,224 @@
+/*
+ * lvmc.h -- C ABI of the MI355X (gfx950) local-volatility Monte Carlo library:
+ * option prices under the Dupire local-volatility model and the adjoint
+ * sensitivities of a book's value to every node of the volatility grid.
+ *
+ * Method (arXiv 2002.02481, "Sensitivity Analysis in the Dupire Local
+ * Volatility Model with Tensorflow"):
+ *   - the asset follows dX/X = sigma(X,t) dW with zero rates (Sec. IV-A, the SDE);
+ *   - an explicit Euler scheme (Sec. IV-A) on y = ln(X/X0) with Ito drift:
+ *       y_{n+1} = y_n - sigma_n^2 dt / 2 + sigma_n sqrt(dt) Z_n,  y_0 = 0,
+ *     with sigma_n = sigma(X0 e^{y_n}, n dt) read at the left end of the step;
+ *   - sigma(S,t) is bilinear in the nodes of a grid {(i dx, j dt)} (Sec. IV-A,
+ *     the grid definition; Sec. IV-D, bilinear interpolation), linear in the
+ *     spot axis coordinate (S, or ln S for a log-spaced axis), flat outside;
+ *   - Z_n are Gaussian (Sec. IV-B, normal generator) from Philox4x32-10 (Salmon
+ *     et al., SC'11) with key = seed and counter = (n/4, path): the four words
+ *     w0..w3 give, through u(w) = ((w >> 9) + 1/2) 2^-23 and Box-Muller,
+ *     Z_{4m}   = r(w0) cos(2 pi u(w1)),  Z_{4m+1} = r(w0) sin(2 pi u(w1)),
+ *     Z_{4m+2} = r(w2) cos(2 pi u(w3)),  Z_{4m+3} = r(w2) sin(2 pi u(w3)),
+ *     r(w) = sqrt(-2 ln u(w));
+ *   - European call/put payoffs at each option's maturity, averaged over
+ *     paths (Sec. IV-B, IV-C): price_k = mean_p payoff_k, std_err_k =
+ *     sqrt(sample variance / P);
+ *   - the gradient of the weighted book value sum_k w_k price_k with respect to
+ *     every vol node by reverse-mode differentiation of the simulation
+ *     (Sec. III, Sec. IV-C), i.e. the average over paths of each path's
+ *     back-propagated derivative; delta = d value / d X0 comes with it.
+ *
+ * Time grid: dt = max_k maturity_k / n_steps; each maturity must be a whole
+ * number of steps (to 1e-9 n_steps), else LV_ERR_STEP.  Path p (0 <= p <
+ * n_paths) consumes Philox counter words (m, p) for m = 0 .. ceil(n_steps/4)-1
+ * only, so results for any path are reproducible in isolation.
+ *
+ * Conventions: all functions return an lv_status; on failure the context's
+ * message (lv_last_error) says why and no output has been written.  "Host"
+ * pointers are ordinary CPU memory owned by the caller; "device" pointers are
+ * HBM of the context's GPU owned by the caller.  Calls that take device
+ * pointers are asynchronous on the context's stream; calls that take host
+ * outputs block until the outputs are written.  A context is not thread-safe:
+ * use one context per host thread / stream.
+ */
+#ifndef LVMC_H
+#define LVMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LV_OK = 0,
+    LV_ERR_ARG = 1,         /* invalid argument (NULL, non-positive size, bad option) */
+    LV_ERR_GRID = 2,        /* invalid grid: fewer than 2x2 nodes, bad axis, sigma not finite and > 0 */
+    LV_ERR_STEP = 3,        /* a maturity is not a whole number of steps */
+    LV_ERR_NOMEM = 4,       /* device workspace could not be allocated */
+    LV_ERR_HIP = 5,         /* a HIP runtime call failed */
+    LV_ERR_UNSUPPORTED = 6  /* valid request this build does not handle (e.g. too many options) */
+} lv_status;
+
+enum { LV_AXIS_LIN = 0, LV_AXIS_LOG = 1 };
+enum { LV_ADJ_DEFAULT = 0, LV_ADJ_NONE = 1, LV_ADJ_STORED = 2, LV_ADJ_CHECKPOINT = 3 };
+
+typedef struct lv_ctx lv_ctx;
+
+/* An axis of n >= 2 inclusive nodes uniform in the axis coordinate between lo
+ * and hi: S for LV_AXIS_LIN, ln S for LV_AXIS_LOG (lo > 0 required).  The time
+ * axis must be LV_AXIS_LIN. */
+typedef struct {
+    int32_t n;
+    int32_t kind;
+    double lo;
+    double hi;
+} lv_axis;
+
+/* The vol grid (Sec. IV-A): sigma[i * time.n + j] is the node at spot node i and
+ * time node j (row-major [spot.n][time.n]). */
+typedef struct {
+    lv_axis spot;
+    lv_axis time;
+} lv_grid;
+
+/* A book of European options on one underlying (host arrays of n_opt entries).
+ * weight: cotangent of each option in the book value (NULL = all 1). */
+typedef struct {
+    int32_t n_opt;
+    const int32_t *is_put;
+    const double *strike;
+    const double *maturity;
+    const double *weight;
+} lv_book;
+
+/* Execution options.  Zero-initialised fields take defaults. */
+typedef struct {
+    int32_t precision;      /* 32 (FP32 stepping and adjoint, FP64 cross-path sums) or 64; default 32 */
+    int32_t adjoint;        /* LV_ADJ_NONE (price only), LV_ADJ_STORED (all states kept in HBM),
+                               LV_ADJ_CHECKPOINT (states every ckpt_every steps, segments recomputed
+                               from the Philox counters); LV_ADJ_DEFAULT = LV_ADJ_STORED */
+    int32_t ckpt_every;     /* checkpoint segment length: 8, 16 or 32 steps; default 16 */
+    int32_t use_graph;      /* 1: capture the launch sequence in a hipGraph per shape and replay it */
+    int32_t block;          /* threads per block, a multiple of 64 in [64, 1024]; 0 = tuned default */
+    int32_t blocks_per_cu;  /* persistent blocks per compute unit; 0 = tuned default */
+    int32_t copies;         /* privatised copies of the LDS gradient histogram (1..16); 0 = default */
+    int32_t window;         /* steps per LDS table/histogram window (multiple of 4); 0 = default */
+    int32_t profile;        /* 1: time every kernel with hipEvents (eager launches only), read back
+                               with lv_kernel_times */
+} lv_opts;
+
+/* Create a context on HIP device `device` that launches on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The context owns a device
+ * workspace that grows on demand and is freed by lv_destroy. */
+lv_status lv_create(lv_ctx **out, int device, void *hip_stream);
+void lv_destroy(lv_ctx *ctx);
+lv_status lv_set_stream(lv_ctx *ctx, void *hip_stream);
+
+/* Message of the last failed call on ctx (ctx may be NULL: the last failure of
+ * a call made without a usable context on this thread).  Never NULL. */
+const char *lv_last_error(const lv_ctx *ctx);
+
+/* Host-side validation of a request, with no GPU access: returns what the
+ * pricing calls would return before launching anything.  sigma (host) may be
+ * NULL to skip the node checks. */
+lv_status lv_check(const lv_grid *grid, const double *sigma, double spot, const lv_book *book,
+                   int64_t n_paths, int32_t n_steps, const lv_opts *opts);
+
+/* Price, standard error, vol-grid gradient and delta of a book (the fused call).
+ * sigma: host [I*J].  price, std_err: host [n_opt].  grad: host [I*J] gradient of
+ * sum_k weight_k price_k, or NULL to skip (then the adjoint is not run).
+ * delta: host [1] d(book value)/d spot, or NULL.  Blocks until done. */
+lv_status lv_price_and_grad(lv_ctx *ctx, const lv_grid *grid, const double *sigma, double spot,
+                            const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                            const lv_opts *opts, double *price, double *std_err, double *grad,
+                            double *delta);
+
+/* The same for n_surf surfaces on the same Philox streams (common random
+ * numbers): sigmas host [n_surf][I*J]; prices, std_errs host [n_surf][n_opt];
+ * grads host [n_surf][I*J] or NULL; deltas host [n_surf] or NULL. */
+lv_status lv_price_and_grad_batch(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
+                                  const double *sigmas, double spot, const lv_book *book,
+                                  int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                  const lv_opts *opts, double *prices, double *std_errs,
+                                  double *grads, double *deltas);
+
+/* Device-resident form of lv_price_and_grad_batch, asynchronous on the
+ * context's stream: sigmas_dev [n_surf][I*J] FP64 device; prices_dev,
+ * std_errs_dev [n_surf][n_opt], grads_dev [n_surf][I*J] (or NULL), deltas_dev
+ * [n_surf] (or NULL) FP64 device.  The book stays a host description. */
+lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
+                                const double *sigmas_dev, double spot, const lv_book *book,
+                                int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                const lv_opts *opts, double *prices_dev, double *std_errs_dev,
+                                double *grads_dev, double *deltas_dev);
+
+/* Bytes of the path-state buffer the split calls use: n_steps planes of
+ * n_paths values (float for precision 32, double for 64), plane n holding
+ * y_{n+1} of every path (path index contiguous). */
+lv_status lv_states_bytes(int32_t precision, int64_t n_paths, int32_t n_steps, size_t *bytes);
+
+/* Split forward (for autograd): simulate, write every state into states_dev
+ * (device, caller-owned, lv_states_bytes long) and per-option price and
+ * std_err (device [n_opt] FP64).  Asynchronous on the context's stream.
+ * The book's weights are ignored here. */
+lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                         const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                         int32_t precision, void *states_dev, double *price_dev,
+                         double *std_err_dev);
+
+/* Split backward: from the states of lv_forward_dev (same arguments) and a
+ * device cotangent [n_opt] (d loss / d price_k), write grad_dev [I*J] =
+ * sum_k cotangent_k d price_k / d sigma and, if non-NULL, delta_dev [1].
+ * Asynchronous on the context's stream.  The book's weights are ignored. */
+lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                          const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                          int32_t precision, const void *states_dev, const double *cotangent_dev,
+                          double *grad_dev, double *delta_dev);
+
+/* Test support: Philox words of paths p0 .. p0+n_paths-1 for counter blocks
+ * m0 .. m0+n_m-1 into words_dev (device uint32 [n_paths][n_m][4]). */
+lv_status lv_debug_philox(lv_ctx *ctx, uint64_t seed, uint64_t m0, int32_t n_m, uint64_t p0,
+                          int64_t n_paths, uint32_t *words_dev);
+
+/* Test support: normals Z_n, n < n_steps, of paths p0 .. p0+n_paths-1 as the
+ * kernels draw them, into z_dev (device [n_paths][n_steps], float for precision
+ * 32, double for 64). */
+lv_status lv_debug_normals(lv_ctx *ctx, int32_t precision, uint64_t seed, uint64_t p0,
+                           int64_t n_paths, int32_t n_steps, void *z_dev);
+
+/* Launch facts of the last pricing call on ctx, so tests can recompute the
+ * partial sums of single blocks: block b handled the path tiles t = b, b + n_blocks,
+ * ... of tile_paths paths each. */
+typedef struct {
+    int32_t n_blocks;
+    int32_t block;
+    int32_t tile_paths;
+    int32_t waves_per_block;
+    int32_t fixed_point_bits;   /* F of the FP32/FP64 fixed-point gradient histogram (last surface) */
+    int32_t adjoint;
+    int32_t precision;
+    int32_t graph_replayed;     /* 1 if the last call replayed a captured graph */
+    int64_t overflow_terms;     /* reserved: 0 */
+} lv_run_info;
+
+lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info);
+
+/* Kernel kinds timed when lv_opts.profile is set. */
+enum { LV_K_FWD = 0, LV_K_REV = 1, LV_K_FUSED = 2, LV_K_MERGE = 3, LV_K_ZERO = 4, LV_K_COUNT = 5 };
+
+/* Accumulated device time (ms, from hipEvents on the context's stream) and launch
+ * counts per kernel kind, over all profiled calls since the last reset; waits
+ * for the stream.  ms and counts are host arrays of LV_K_COUNT entries.  reset = 1
+ * clears the totals after reading. */
+lv_status lv_kernel_times(lv_ctx *ctx, double *ms, int64_t *counts, int32_t reset);
+
+/* Test support: copy the per-block gradient partial sums of the last surface of
+ * the last pricing call (unnormalised FP64, [n_blocks][I*J], before the merge)
+ * to host memory; host_len is the number of doubles host_out holds. */
+lv_status lv_debug_block_grads(lv_ctx *ctx, double *host_out, size_t host_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LVMC_H */

@@ -42,6 +42,14 @@ class OracleError(RuntimeError):
     pass
 
 
+def default_threads() -> int:
+    """Worker threads: LV_ORACLE_THREADS if set, else the host cores, at most 16."""
+    env = os.environ.get("LV_ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def _surface_args(surface):
     sa, ta = surface.spot_axis, surface.time_axis
     return (C.c_int32(sa.n), C.c_int32(sa.kind), C.c_double(sa.lo), C.c_double(sa.hi),
@@ -133,7 +141,7 @@ class Oracle:
         """Unnormalised sums of payoff, payoff^2, grid gradient and d/dy_0 of the
         weighted book value over the given half-open path ranges."""
         if n_threads <= 0:
-            n_threads = os.cpu_count() or 1
+            n_threads = default_threads()
         rg = np.ascontiguousarray(np.asarray(ranges, dtype=np.int64).reshape(-1, 2))
         s1, s2 = np.zeros(book.n), np.zeros(book.n)
         G = surface.spot_axis.n * surface.time_axis.n

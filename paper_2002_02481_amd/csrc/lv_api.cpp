@@ -1,0 +1,805 @@
+// lv_api.cpp -- host runtime and C ABI of the local-vol Monte Carlo library
+// (include/lvmc.h): request validation, launch planning, the device workspace,
+// hipGraph capture/replay and the fused, batched and split entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lv_internal.h"
+#include "lvmc.h"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+// Everything derived from one request: the time table, the book in maturity
+// order, the launch shape.
+struct Plan {
+    int I = 0, J = 0, N = 0, axis = 0;
+    double inv_du = 0, a_off = 0, spot = 0, dt = 0, sqrt_dt = 0;
+    long long P = 0;
+    uint64_t seed = 0;
+    int n_opt = 0, n_taps = 0;
+    std::vector<int> tj, tap_step, tap_first, tap_count, opt_put, opt_orig;
+    std::vector<double> ta, opt_strike, weight;
+    int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;
+    int block = 256, blocks = 0, n_tiles = 0, W = 16, K = 8, S = 32;
+    int G = 0, Q = 0;
+};
+
+}  // namespace
+
+struct lv_ctx {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    int n_cu = 256;
+    size_t max_lds = 65536;
+    std::string err = "no error";
+    Buf planbuf, part, seg, overflow, states, ckpt, sig_stage, out_stage;
+    std::vector<char> plan_bytes;     // what planbuf holds
+    lv_run_info info{};
+    int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
+    // kernel timing (lv_opts.profile)
+    struct Timed {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> event_pool;
+    double k_ms[LV_K_COUNT] = {0};
+    int64_t k_count[LV_K_COUNT] = {0};
+    // graph cache (one entry)
+    std::string graph_key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+};
+
+namespace {
+
+lv_status fail(lv_ctx *ctx, lv_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    g_last_error = buf;
+    return st;
+}
+
+#define HIPCHECK(ctx, call)                                                                 \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, LV_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+lv_status ensure(lv_ctx *ctx, Buf &b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.n >= bytes) return LV_OK;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(ctx->stream());
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(ctx, LV_ERR_NOMEM, "device workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    b.n = bytes;
+    return LV_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// ---------------------------------------------------------------------------
+// Validation and planning (host only, no GPU access)
+// ---------------------------------------------------------------------------
+lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const double *sigma_host,
+                       double spot, const lv_book *book, int64_t n_paths, int32_t n_steps,
+                       uint64_t seed, const lv_opts *opts, int n_cu, size_t max_lds, Plan &pl) {
+    if (!grid) return fail(ctx, LV_ERR_ARG, "grid is NULL");
+    const lv_axis &sa = grid->spot, &ta = grid->time;
+    if (sa.n < 2 || ta.n < 2) return fail(ctx, LV_ERR_GRID, "grid needs at least 2x2 nodes (got %dx%d)", sa.n, ta.n);
+    if ((long long)sa.n * ta.n > 100000) return fail(ctx, LV_ERR_UNSUPPORTED, "grid of %d x %d nodes is too large", sa.n, ta.n);
+    if (sa.kind != LV_AXIS_LIN && sa.kind != LV_AXIS_LOG) return fail(ctx, LV_ERR_GRID, "unknown spot axis kind %d", sa.kind);
+    if (ta.kind != LV_AXIS_LIN) return fail(ctx, LV_ERR_GRID, "time axis must be linear");
+    if (!(std::isfinite(sa.lo) && std::isfinite(sa.hi) && sa.hi > sa.lo)) return fail(ctx, LV_ERR_GRID, "spot axis needs finite lo < hi");
+    if (sa.kind == LV_AXIS_LOG && !(sa.lo > 0)) return fail(ctx, LV_ERR_GRID, "log spot axis needs lo > 0");
+    if (!(std::isfinite(ta.lo) && std::isfinite(ta.hi) && ta.hi > ta.lo)) return fail(ctx, LV_ERR_GRID, "time axis needs finite lo < hi");
+    const long long G = (long long)sa.n * ta.n;
+    if (sigma_host) {
+        for (long long q = 0; q < G * n_surf; ++q)
+            if (!finite_pos(sigma_host[q])) return fail(ctx, LV_ERR_GRID, "sigma node %lld is not finite and positive", q % G);
+    }
+    if (!finite_pos(spot)) return fail(ctx, LV_ERR_ARG, "spot must be finite and positive");
+    if (!book || book->n_opt < 1 || !book->is_put || !book->strike || !book->maturity)
+        return fail(ctx, LV_ERR_ARG, "book needs n_opt >= 1 and non-NULL is_put, strike, maturity");
+    if (book->n_opt > 256) return fail(ctx, LV_ERR_UNSUPPORTED, "at most 256 options per book (got %d)", book->n_opt);
+    if (n_paths < 2 || n_paths > (1ll << 40)) return fail(ctx, LV_ERR_ARG, "n_paths must be in [2, 2^40]");
+    if (n_steps < 1 || n_steps > 1000000) return fail(ctx, LV_ERR_ARG, "n_steps must be in [1, 1e6]");
+    if (n_surf < 1) return fail(ctx, LV_ERR_ARG, "n_surf must be >= 1");
+    lv_opts o{};
+    if (opts) o = *opts;
+    if (o.precision == 0) o.precision = 32;
+    if (o.precision != 32 && o.precision != 64) return fail(ctx, LV_ERR_ARG, "precision must be 32 or 64");
+    if (o.adjoint < 0 || o.adjoint > 3) return fail(ctx, LV_ERR_ARG, "unknown adjoint mode %d", o.adjoint);
+    if (o.adjoint == LV_ADJ_DEFAULT) o.adjoint = LV_ADJ_STORED;
+    if (o.ckpt_every == 0) o.ckpt_every = 16;
+    if (o.ckpt_every != 8 && o.ckpt_every != 16 && o.ckpt_every != 32)
+        return fail(ctx, LV_ERR_ARG, "ckpt_every must be 8, 16 or 32");
+    if (o.block != 0 && (o.block % 64 != 0 || o.block < 64 || o.block > 1024))
+        return fail(ctx, LV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return fail(ctx, LV_ERR_ARG, "blocks_per_cu must be in [0, 64]");
+    if (o.copies < 0 || o.copies > 16) return fail(ctx, LV_ERR_ARG, "copies must be in [0, 16]");
+    if (o.window < 0 || o.window % 4 != 0 || o.window > 64) return fail(ctx, LV_ERR_ARG, "window must be a multiple of 4 in [4, 64]");
+
+    double tmax = 0.0;
+    for (int k = 0; k < book->n_opt; ++k) {
+        if (!finite_pos(book->strike[k])) return fail(ctx, LV_ERR_ARG, "strike %d must be finite and positive", k);
+        if (!finite_pos(book->maturity[k])) return fail(ctx, LV_ERR_ARG, "maturity %d must be finite and positive", k);
+        if (book->is_put[k] != 0 && book->is_put[k] != 1) return fail(ctx, LV_ERR_ARG, "is_put %d must be 0 or 1", k);
+        if (book->weight && !std::isfinite(book->weight[k])) return fail(ctx, LV_ERR_ARG, "weight %d not finite", k);
+        tmax = std::max(tmax, book->maturity[k]);
+    }
+    pl = Plan();
+    pl.I = sa.n;
+    pl.J = ta.n;
+    pl.N = n_steps;
+    pl.axis = sa.kind;
+    pl.spot = spot;
+    pl.dt = tmax / n_steps;
+    pl.sqrt_dt = std::sqrt(pl.dt);
+    pl.P = n_paths;
+    pl.seed = seed;
+    pl.n_opt = book->n_opt;
+    pl.precision = o.precision;
+    pl.adjoint = o.adjoint;
+    pl.seg = o.ckpt_every;
+    pl.profile = o.profile ? 1 : 0;
+    pl.G = (int)G;
+    pl.Q = 2 * pl.n_opt + 1 + pl.G;
+
+    // maturities -> tap steps
+    std::vector<int> steps(pl.n_opt);
+    for (int k = 0; k < pl.n_opt; ++k) {
+        const double x = book->maturity[k] / pl.dt;
+        const double r = std::floor(x + 0.5);
+        if (std::fabs(x - r) > 1e-9 * n_steps || r < 1.0)
+            return fail(ctx, LV_ERR_STEP, "maturity %d (%.17g) is not a whole number of steps of %.17g", k,
+                        book->maturity[k], pl.dt);
+        steps[k] = (int)r;
+    }
+    std::vector<int> order(pl.n_opt);
+    for (int k = 0; k < pl.n_opt; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return steps[a] < steps[b]; });
+    for (int q = 0; q < pl.n_opt; ++q) {
+        const int k = order[q];
+        pl.opt_orig.push_back(k);
+        pl.opt_put.push_back(book->is_put[k]);
+        pl.opt_strike.push_back(book->strike[k]);
+        if (q == 0 || steps[k] != pl.tap_step.back()) {
+            pl.tap_step.push_back(steps[k]);
+            pl.tap_first.push_back(q);
+            pl.tap_count.push_back(0);
+        }
+        pl.tap_count.back() += 1;
+    }
+    pl.n_taps = (int)pl.tap_step.size();
+    for (int k = 0; k < pl.n_opt; ++k) pl.weight.push_back(book->weight ? book->weight[k] : 1.0);
+
+    // spot axis coordinate -> grid coordinate
+    double u0, u1;
+    if (sa.kind == LV_AXIS_LOG) {
+        u0 = std::log(sa.lo);
+        u1 = std::log(sa.hi);
+    } else {
+        u0 = sa.lo;
+        u1 = sa.hi;
+    }
+    const double du = (u1 - u0) / (sa.n - 1);
+    pl.inv_du = 1.0 / du;
+    pl.a_off = sa.kind == LV_AXIS_LOG ? (std::log(spot) - u0) / du : -u0 / du;
+
+    // time cell of every step: b = clamp((t_n - t_0)/dtau, 0, J-1), j = min(floor b, J-2)
+    const double dtau = (ta.hi - ta.lo) / (ta.n - 1);
+    pl.tj.resize(n_steps);
+    pl.ta.resize(n_steps);
+    for (int n = 0; n < n_steps; ++n) {
+        double b = (n * pl.dt - ta.lo) / dtau;
+        b = std::min(std::max(b, 0.0), (double)(ta.n - 1));
+        int j = std::min((int)std::floor(b), ta.n - 2);
+        pl.tj[n] = j;
+        pl.ta[n] = b - j;
+    }
+
+    // launch shape
+    pl.block = o.block ? o.block : 256;
+    pl.K = o.copies ? o.copies : 8;
+    pl.W = o.window ? o.window : 16;
+    if (pl.adjoint == LV_ADJ_CHECKPOINT) pl.W = pl.seg;
+    const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
+    auto need = [&]() {
+        size_t a = lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, pl.block, pl.W, pl.K);
+        size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, pl.block, pl.W, pl.K);
+        return std::max(a, b);
+    };
+    // shrink histogram copies, then the window, until the block fits in LDS
+    while (need() > max_lds && pl.K > 1 && !o.copies) pl.K /= 2;
+    while (need() > max_lds && pl.W > 4 && !o.window && pl.adjoint != LV_ADJ_CHECKPOINT) pl.W /= 2;
+    if (need() > max_lds)
+        return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)", need(), max_lds);
+    pl.n_tiles = (int)((n_paths + pl.block - 1) / pl.block);
+    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
+    pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * bpc);
+    pl.S = std::min(32, pl.blocks);
+    return LV_OK;
+}
+
+int host_fixed_point_bits(const Plan &pl) {
+    const double qmax = lvk::fixed_point_qmax(pl.precision, pl.block, pl.K);
+    double scale = 0.0;
+    for (int q = 0; q < pl.n_opt; ++q)
+        scale += std::fabs(pl.weight[pl.opt_orig[q]]) * std::max(pl.spot, pl.opt_strike[q]);
+    const int fmaxb = pl.precision == 64 ? 62 : 40;
+    if (!(scale > 0.0)) return fmaxb;
+    const int F = std::ilogb(qmax / (8.0 * scale));
+    return std::max(-30, std::min(fmaxb, F));
+}
+
+// Pack the plan's device tables; upload only when they change.
+struct Tables {
+    const int *tj, *tap_step, *tap_first, *tap_count, *opt_put, *opt_orig;
+    const double *ta, *opt_strike, *weight;
+};
+
+template <typename T>
+void put(std::vector<char> &v, const std::vector<T> &x, size_t &off) {
+    off = (v.size() + 15) & ~(size_t)15;
+    v.resize(off + x.size() * sizeof(T) + 16);
+    if (!x.empty()) std::memcpy(v.data() + off, x.data(), x.size() * sizeof(T));
+}
+
+lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
+    std::vector<char> v;
+    size_t o[9];
+    put(v, pl.tj, o[0]);
+    put(v, pl.tap_step, o[1]);
+    put(v, pl.tap_first, o[2]);
+    put(v, pl.tap_count, o[3]);
+    put(v, pl.opt_put, o[4]);
+    put(v, pl.opt_orig, o[5]);
+    put(v, pl.ta, o[6]);
+    put(v, pl.opt_strike, o[7]);
+    put(v, pl.weight, o[8]);
+    lv_status st = ensure(ctx, ctx->planbuf, v.size());
+    if (st != LV_OK) return st;
+    if (v != ctx->plan_bytes) {
+        // the stream may still read the old tables
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
+        HIPCHECK(ctx, hipMemcpy(ctx->planbuf.p, v.data(), v.size(), hipMemcpyHostToDevice));
+        ctx->plan_bytes.swap(v);
+    }
+    char *b = (char *)ctx->planbuf.p;
+    t.tj = (const int *)(b + o[0]);
+    t.tap_step = (const int *)(b + o[1]);
+    t.tap_first = (const int *)(b + o[2]);
+    t.tap_count = (const int *)(b + o[3]);
+    t.opt_put = (const int *)(b + o[4]);
+    t.opt_orig = (const int *)(b + o[5]);
+    t.ta = (const double *)(b + o[6]);
+    t.opt_strike = (const double *)(b + o[7]);
+    t.weight = (const double *)(b + o[8]);
+    return LV_OK;
+}
+
+lvk::Args make_args(const Plan &pl, const Tables &t, const double *sigma_dev) {
+    lvk::Args a{};
+    a.I = pl.I;
+    a.J = pl.J;
+    a.N = pl.N;
+    a.axis = pl.axis;
+    a.inv_du = pl.inv_du;
+    a.a_off = pl.a_off;
+    a.spot = pl.spot;
+    a.dt = pl.dt;
+    a.sqrt_dt = pl.sqrt_dt;
+    a.sigma = sigma_dev;
+    a.tj = t.tj;
+    a.ta = t.ta;
+    a.P = pl.P;
+    a.key0 = (unsigned)(pl.seed & 0xFFFFFFFFu);
+    a.key1 = (unsigned)(pl.seed >> 32);
+    a.n_opt = pl.n_opt;
+    a.n_taps = pl.n_taps;
+    a.tap_step = t.tap_step;
+    a.tap_first = t.tap_first;
+    a.tap_count = t.tap_count;
+    a.opt_put = t.opt_put;
+    a.opt_strike = t.opt_strike;
+    a.opt_orig = t.opt_orig;
+    a.cot = t.weight;
+    a.Q = pl.Q;
+    a.n_tiles = pl.n_tiles;
+    a.W = pl.W;
+    a.K = pl.K;
+    a.seg = pl.seg;
+    return a;
+}
+
+size_t real_bytes(int precision) { return precision == 64 ? 8 : 4; }
+
+// Workspace for the fused paths.
+lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
+    lv_status st;
+    if ((st = ensure(ctx, ctx->part, (size_t)pl.blocks * pl.Q * 8)) != LV_OK) return st;
+    if ((st = ensure(ctx, ctx->seg, (size_t)pl.S * pl.Q * 8)) != LV_OK) return st;
+    if ((st = ensure(ctx, ctx->overflow, (size_t)pl.G * 8)) != LV_OK) return st;
+    if (adjoint && pl.adjoint == LV_ADJ_STORED) {
+        const size_t b = (size_t)pl.N * (size_t)pl.P * real_bytes(pl.precision);
+        if ((st = ensure(ctx, ctx->states, b)) != LV_OK) return st;
+    }
+    if (adjoint && pl.adjoint == LV_ADJ_CHECKPOINT) {
+        const size_t nseg = (pl.N + pl.seg - 1) / pl.seg;
+        const size_t b = nseg * (size_t)pl.blocks * pl.block * real_bytes(pl.precision);
+        if ((st = ensure(ctx, ctx->ckpt, b)) != LV_OK) return st;
+    }
+    return LV_OK;
+}
+
+hipEvent_t take_event(lv_ctx *ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` on the context's stream, bracketed by events when profiling.
+template <typename Fn>
+hipError_t timed(lv_ctx *ctx, bool profile, int kind, Fn fn) {
+    if (!profile) return fn();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, ctx->stream());
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, ctx->stream());
+    if (e != hipSuccess) return e;
+    ctx->pending.push_back({a, b, kind});
+    return hipSuccess;
+}
+
+lv_status collect_times(lv_ctx *ctx) {
+    if (ctx->pending.empty()) return LV_OK;
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
+    for (auto &t : ctx->pending) {
+        float ms = 0.f;
+        HIPCHECK(ctx, hipEventElapsedTime(&ms, t.a, t.b));
+        ctx->k_ms[t.kind] += ms;
+        ctx->k_count[t.kind] += 1;
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->pending.clear();
+    return LV_OK;
+}
+
+// Launch the whole path for one surface (no allocation, no sync): capturable.
+hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *sigma_dev,
+                           bool adjoint, double *price, double *stderr_, double *grad,
+                           double *delta, bool capturing) {
+    hipStream_t st = ctx->stream();
+    lvk::Args a = make_args(pl, t, sigma_dev);
+    a.part = (double *)ctx->part.p;
+    a.overflow = (double *)ctx->overflow.p;
+    a.states = ctx->states.p;
+    a.ckpt = ctx->ckpt.p;
+    const bool prof = pl.profile && !capturing;
+    hipError_t e;
+    if (!adjoint) {
+        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, false, pl.blocks, pl.block, st); });
+        if (e != hipSuccess) return e;
+        return timed(ctx, prof, LV_K_MERGE, [&] {
+            return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow,
+                                     pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, nullptr,
+                                     nullptr, st);
+        });
+    }
+    e = timed(ctx, prof, LV_K_ZERO, [&] { return lvk::launch_zero(a.overflow, pl.G, st); });
+    if (e != hipSuccess) return e;
+    if (pl.adjoint == LV_ADJ_STORED) {
+        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st); });
+        if (e != hipSuccess) return e;
+        e = timed(ctx, prof, LV_K_REV, [&] { return lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st); });
+        if (e != hipSuccess) return e;
+    } else {
+        e = timed(ctx, prof, LV_K_FUSED, [&] { return lvk::launch_fused_ckpt(a, pl.precision, pl.blocks, pl.block, st); });
+        if (e != hipSuccess) return e;
+    }
+    return timed(ctx, prof, LV_K_MERGE, [&] {
+        return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
+                                 pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, grad, delta, st);
+    });
+}
+
+void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
+    ctx->last_Q = pl.Q;
+    ctx->last_G = pl.G;
+    ctx->last_nopt = pl.n_opt;
+    ctx->info.n_blocks = pl.blocks;
+    ctx->info.block = pl.block;
+    ctx->info.tile_paths = pl.block;
+    ctx->info.waves_per_block = pl.block / 64;
+    ctx->info.fixed_point_bits = host_fixed_point_bits(pl);
+    ctx->info.adjoint = adjoint ? pl.adjoint : LV_ADJ_NONE;
+    ctx->info.precision = pl.precision;
+    ctx->info.graph_replayed = replayed ? 1 : 0;
+    ctx->info.overflow_terms = 0;
+}
+
+std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf, bool adjoint) {
+    std::string k;
+    char buf[128];
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I, pl.J, pl.N,
+             pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
+             pl.blocks, pl.W, pl.K, pl.spot, pl.dt, n_surf);
+    k += buf;
+    k += adjoint ? "A|" : "F|";
+    for (int i = 0; i < n_ptrs; ++i) {
+        snprintf(buf, sizeof buf, "%p|", ptrs[i]);
+        k += buf;
+    }
+    return k;
+}
+
+lv_status run_dev(lv_ctx *ctx, const Plan &pl, int n_surf, const double *sigmas_dev,
+                  bool adjoint, bool use_graph, double *prices, double *stderrs, double *grads,
+                  double *deltas) {
+    lv_status s;
+    Tables t;
+    if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
+    if ((s = ensure_workspace(ctx, pl, adjoint)) != LV_OK) return s;
+    auto enqueue_all = [&]() -> hipError_t {
+        for (int k = 0; k < n_surf; ++k) {
+            hipError_t e = enqueue_surface(ctx, pl, t, sigmas_dev + (size_t)k * pl.G, adjoint,
+                                           prices + (size_t)k * pl.n_opt, stderrs + (size_t)k * pl.n_opt,
+                                           grads ? grads + (size_t)k * pl.G : nullptr,
+                                           deltas ? deltas + k : nullptr, use_graph);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (!use_graph) {
+        hipError_t e = enqueue_all();
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        record_info(ctx, pl, adjoint, false);
+        return LV_OK;
+    }
+    const void *ptrs[] = {sigmas_dev, prices, stderrs, grads, deltas, ctx->planbuf.p, ctx->part.p,
+                          ctx->seg.p, ctx->overflow.p, ctx->states.p, ctx->ckpt.p};
+    std::string key = graph_key(pl, ptrs, 11, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
+    bool replay = ctx->graph_exec && key == ctx->graph_key;
+    if (!replay) {
+        if (ctx->graph_exec) {
+            (void)hipGraphExecDestroy(ctx->graph_exec);
+            ctx->graph_exec = nullptr;
+        }
+        if (ctx->graph) {
+            (void)hipGraphDestroy(ctx->graph);
+            ctx->graph = nullptr;
+        }
+        ctx->graph_key.clear();
+        HIPCHECK(ctx, hipStreamBeginCapture(ctx->stream(), hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_all();
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->stream(), &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(ctx, LV_ERR_HIP, "graph capture failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
+        }
+        ctx->graph = g;
+        HIPCHECK(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+        ctx->graph_key = key;
+    }
+    HIPCHECK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream()));
+    record_info(ctx, pl, adjoint, replay);
+    return LV_OK;
+}
+
+int device_cus(int device, size_t *max_lds) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, device) != hipSuccess) return 256;
+    if (max_lds) *max_lds = std::min<size_t>(pr.sharedMemPerBlock, 65536);
+    return pr.multiProcessorCount;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+lv_status lv_create(lv_ctx **out, int device, void *hip_stream) {
+    if (!out) return fail(nullptr, LV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(nullptr, LV_ERR_HIP, "no HIP device available (%s)", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, LV_ERR_ARG, "device %d out of range (%d devices)", device, n);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, LV_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    lv_ctx *c = new lv_ctx();
+    c->device = device;
+    c->user_stream = (hipStream_t)hip_stream;
+    c->n_cu = device_cus(device, &c->max_lds);
+    e = hipStreamCreate(&c->own_stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(nullptr, LV_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return LV_OK;
+}
+
+void lv_destroy(lv_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream());
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    for (auto &t : ctx->pending) {
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->seg, &ctx->overflow, &ctx->states, &ctx->ckpt,
+                   &ctx->sig_stage, &ctx->out_stage};
+    for (Buf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+}
+
+lv_status lv_set_stream(lv_ctx *ctx, void *hip_stream) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    ctx->user_stream = (hipStream_t)hip_stream;
+    return LV_OK;
+}
+
+const char *lv_last_error(const lv_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+lv_status lv_check(const lv_grid *grid, const double *sigma, double spot, const lv_book *book,
+                   int64_t n_paths, int32_t n_steps, const lv_opts *opts) {
+    Plan pl;
+    return plan_request(nullptr, grid, 1, sigma, spot, book, n_paths, n_steps, 0, opts, 256, 65536, pl);
+}
+
+lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
+                                const double *sigmas_dev, double spot, const lv_book *book,
+                                int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                const lv_opts *opts, double *prices_dev, double *std_errs_dev,
+                                double *grads_dev, double *deltas_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigmas_dev || !prices_dev || !std_errs_dev) return fail(ctx, LV_ERR_ARG, "sigmas, prices and std_errs are required");
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, n_surf, nullptr, spot, book, n_paths, n_steps, seed, opts,
+                               ctx->n_cu, ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    const bool adjoint = grads_dev || deltas_dev;
+    if (adjoint && pl.adjoint == LV_ADJ_NONE)
+        return fail(ctx, LV_ERR_ARG, "gradient or delta requested with adjoint mode NONE");
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    return run_dev(ctx, pl, n_surf, sigmas_dev, adjoint, opts && opts->use_graph, prices_dev,
+                   std_errs_dev, grads_dev, deltas_dev);
+}
+
+lv_status lv_price_and_grad_batch(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
+                                  const double *sigmas, double spot, const lv_book *book,
+                                  int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                  const lv_opts *opts, double *prices, double *std_errs,
+                                  double *grads, double *deltas) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigmas || !prices || !std_errs) return fail(ctx, LV_ERR_ARG, "sigmas, prices and std_errs are required");
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, n_surf, sigmas, spot, book, n_paths, n_steps, seed, opts,
+                               ctx->n_cu, ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    const bool adjoint = grads || deltas;
+    if (adjoint && pl.adjoint == LV_ADJ_NONE)
+        return fail(ctx, LV_ERR_ARG, "gradient or delta requested with adjoint mode NONE");
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    const size_t nsig = (size_t)n_surf * pl.G;
+    const size_t per = (size_t)2 * pl.n_opt + 1 + pl.G;   // prices, stderrs, delta, grad
+    if ((s = ensure(ctx, ctx->sig_stage, nsig * 8)) != LV_OK) return s;
+    if ((s = ensure(ctx, ctx->out_stage, (size_t)n_surf * per * 8)) != LV_OK) return s;
+    hipStream_t st = ctx->stream();
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->sig_stage.p, sigmas, nsig * 8, hipMemcpyHostToDevice, st));
+    double *o = (double *)ctx->out_stage.p;
+    double *d_price = o, *d_se = o + (size_t)n_surf * pl.n_opt, *d_delta = o + (size_t)2 * n_surf * pl.n_opt;
+    double *d_grad = d_delta + n_surf;
+    s = run_dev(ctx, pl, n_surf, (const double *)ctx->sig_stage.p, adjoint, opts && opts->use_graph,
+                d_price, d_se, grads ? d_grad : nullptr, adjoint ? d_delta : nullptr);
+    if (s != LV_OK) return s;
+    std::vector<double> h((size_t)n_surf * per);
+    HIPCHECK(ctx, hipMemcpyAsync(h.data(), o, h.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(ctx, hipStreamSynchronize(st));
+    std::memcpy(prices, h.data(), (size_t)n_surf * pl.n_opt * 8);
+    std::memcpy(std_errs, h.data() + (size_t)n_surf * pl.n_opt, (size_t)n_surf * pl.n_opt * 8);
+    if (deltas) std::memcpy(deltas, h.data() + (size_t)2 * n_surf * pl.n_opt, (size_t)n_surf * 8);
+    if (grads) std::memcpy(grads, h.data() + (size_t)2 * n_surf * pl.n_opt + n_surf, (size_t)n_surf * pl.G * 8);
+    return LV_OK;
+}
+
+lv_status lv_price_and_grad(lv_ctx *ctx, const lv_grid *grid, const double *sigma, double spot,
+                            const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                            const lv_opts *opts, double *price, double *std_err, double *grad,
+                            double *delta) {
+    return lv_price_and_grad_batch(ctx, grid, 1, sigma, spot, book, n_paths, n_steps, seed, opts,
+                                   price, std_err, grad, delta);
+}
+
+lv_status lv_states_bytes(int32_t precision, int64_t n_paths, int32_t n_steps, size_t *bytes) {
+    if (!bytes) return fail(nullptr, LV_ERR_ARG, "bytes is NULL");
+    if (precision != 32 && precision != 64) return fail(nullptr, LV_ERR_ARG, "precision must be 32 or 64");
+    if (n_paths < 2 || n_steps < 1) return fail(nullptr, LV_ERR_ARG, "n_paths >= 2 and n_steps >= 1 required");
+    *bytes = (size_t)n_paths * (size_t)n_steps * real_bytes(precision);
+    return LV_OK;
+}
+
+lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                         const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                         int32_t precision, void *states_dev, double *price_dev,
+                         double *std_err_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigma_dev || !states_dev || !price_dev || !std_err_dev)
+        return fail(ctx, LV_ERR_ARG, "sigma, states, price and std_err are required");
+    lv_opts o{};
+    o.precision = precision;
+    o.adjoint = LV_ADJ_STORED;
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, 1, nullptr, spot, book, n_paths, n_steps, seed, &o, ctx->n_cu,
+                               ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    Tables t;
+    if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
+    if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
+    hipStream_t st = ctx->stream();
+    lvk::Args a = make_args(pl, t, sigma_dev);
+    a.part = (double *)ctx->part.p;
+    a.overflow = (double *)ctx->overflow.p;
+    a.states = states_dev;
+    hipError_t e = lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st);
+    if (e == hipSuccess)
+        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
+                              pl.G, t.opt_orig, pl.P, pl.spot, price_dev, std_err_dev, nullptr, nullptr, st);
+    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    record_info(ctx, pl, false, false);
+    return LV_OK;
+}
+
+lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                          const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                          int32_t precision, const void *states_dev, const double *cotangent_dev,
+                          double *grad_dev, double *delta_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigma_dev || !states_dev || !cotangent_dev || !grad_dev)
+        return fail(ctx, LV_ERR_ARG, "sigma, states, cotangent and grad are required");
+    lv_opts o{};
+    o.precision = precision;
+    o.adjoint = LV_ADJ_STORED;
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, 1, nullptr, spot, book, n_paths, n_steps, seed, &o, ctx->n_cu,
+                               ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    Tables t;
+    if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
+    if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
+    // the reverse writes no payoff sums: the merge reads zeros there
+    if ((s = ensure(ctx, ctx->out_stage, (size_t)2 * pl.n_opt * 8)) != LV_OK) return s;
+    hipStream_t st = ctx->stream();
+    lvk::Args a = make_args(pl, t, sigma_dev);
+    a.part = (double *)ctx->part.p;
+    a.overflow = (double *)ctx->overflow.p;
+    a.states = const_cast<void *>(states_dev);
+    a.cot = cotangent_dev;
+    hipError_t e = lvk::launch_zero(a.part, (size_t)pl.blocks * pl.Q, st);
+    if (e == hipSuccess) e = lvk::launch_zero(a.overflow, pl.G, st);
+    if (e == hipSuccess) e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
+    double *scratch = (double *)ctx->out_stage.p;
+    if (e == hipSuccess)
+        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
+                              pl.G, t.opt_orig, pl.P, pl.spot, scratch, scratch + pl.n_opt, grad_dev,
+                              delta_dev, st);
+    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    record_info(ctx, pl, true, false);
+    ctx->info.fixed_point_bits = -1000;   // depends on the device cotangent
+    return LV_OK;
+}
+
+lv_status lv_debug_philox(lv_ctx *ctx, uint64_t seed, uint64_t m0, int32_t n_m, uint64_t p0,
+                          int64_t n_paths, uint32_t *words_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!words_dev || n_m < 1 || n_paths < 1) return fail(ctx, LV_ERR_ARG, "bad arguments");
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    hipError_t e = lvk::launch_debug_philox(seed, m0, n_m, p0, n_paths, words_dev, ctx->stream());
+    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
+    return LV_OK;
+}
+
+lv_status lv_debug_normals(lv_ctx *ctx, int32_t precision, uint64_t seed, uint64_t p0,
+                           int64_t n_paths, int32_t n_steps, void *z_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!z_dev || n_paths < 1 || n_steps < 1 || (precision != 32 && precision != 64))
+        return fail(ctx, LV_ERR_ARG, "bad arguments");
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    hipError_t e = lvk::launch_debug_normals(precision, seed, p0, n_paths, n_steps, 1.0, z_dev, ctx->stream());
+    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
+    return LV_OK;
+}
+
+lv_status lv_kernel_times(lv_ctx *ctx, double *ms, int64_t *counts, int32_t reset) {
+    if (!ctx || !ms || !counts) return fail(ctx, LV_ERR_ARG, "ctx, ms and counts are required");
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    lv_status s = collect_times(ctx);
+    if (s != LV_OK) return s;
+    for (int k = 0; k < LV_K_COUNT; ++k) {
+        ms[k] = ctx->k_ms[k];
+        counts[k] = ctx->k_count[k];
+        if (reset) {
+            ctx->k_ms[k] = 0.0;
+            ctx->k_count[k] = 0;
+        }
+    }
+    return LV_OK;
+}
+
+lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info) {
+    if (!ctx || !info) return fail(nullptr, LV_ERR_ARG, "ctx and info are required");
+    *info = ctx->info;
+    return LV_OK;
+}
+
+lv_status lv_debug_block_grads(lv_ctx *ctx, double *host_out, size_t host_len) {
+    if (!ctx || !host_out) return fail(ctx, LV_ERR_ARG, "ctx and host_out are required");
+    const int B = ctx->info.n_blocks, Q = ctx->last_Q, G = ctx->last_G, n_opt = ctx->last_nopt;
+    if (B <= 0 || !ctx->part.p || ctx->info.adjoint == LV_ADJ_NONE)
+        return fail(ctx, LV_ERR_ARG, "no gradient call has run on this context");
+    if (host_len < (size_t)B * G) return fail(ctx, LV_ERR_ARG, "host_out holds %zu doubles, need %zu", host_len, (size_t)B * G);
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    std::vector<double> h((size_t)B * Q);
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
+    HIPCHECK(ctx, hipMemcpy(h.data(), ctx->part.p, h.size() * 8, hipMemcpyDeviceToHost));
+    for (int b = 0; b < B; ++b)
+        std::memcpy(host_out + (size_t)b * G, h.data() + (size_t)b * Q + 2 * n_opt + 1, (size_t)G * 8);
+    return LV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// lv_internal.h -- interface between the host runtime (lv_api.cpp) and the
+// device kernels (lv_kernels.hip) of the local-vol Monte Carlo library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lvk {
+
+// Everything a pricing kernel needs, passed by value.  Option arrays are in
+// tap order (ascending maturity step); opt_orig maps back to caller order.
+struct Args {
+    // grid and time stepping
+    int I, J, N, axis;          // spot nodes, time nodes, steps, spot axis kind (0 lin, 1 log)
+    double inv_du;              // 1 / node spacing in the spot-axis coordinate
+    double a_off;               // grid coordinate a = x * inv_du + a_off (x = S on lin, y on log)
+    double spot, dt, sqrt_dt;
+    const double *sigma;        // [I][J] FP64, this surface
+    const int *tj;              // [N] time cell of step n
+    const double *ta;           // [N] weight of time node tj+1 at step n
+    long long P;                // paths
+    unsigned key0, key1;        // Philox key = seed
+    // book
+    int n_opt, n_taps;
+    const int *tap_step;        // [n_taps] ascending step index of each maturity
+    const int *tap_first;       // [n_taps] first option (tap order) at that step
+    const int *tap_count;       // [n_taps]
+    const int *opt_put;         // [n_opt] tap order
+    const double *opt_strike;   // [n_opt] tap order
+    const int *opt_orig;        // [n_opt] caller index of each option
+    const double *cot;          // [n_opt] cotangent per option, caller order
+    // storage
+    void *states;               // stored planes [N][P]: plane n holds y_{n+1}
+    void *ckpt;                 // checkpoint slots [n_seg][n_blocks * block]
+    // per-block partial records: [n_blocks][Q], Q = 2 n_opt + 1 + I J
+    double *part;
+    int Q;
+    double *overflow;           // [I J] rare large adjoint terms (FP64 global atomics)
+    // tiling
+    int n_tiles;                // path tiles of blockDim paths
+    int W;                      // steps per LDS window (multiple of 4)
+    int K;                      // privatised histogram copies
+    int seg;                    // checkpoint segment (steps)
+};
+
+enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };
+
+// LDS bytes a kernel variant needs for the given shape.
+size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int K);
+// Largest fixed-point term the gradient histogram accepts, for the given shape.
+__host__ __device__ double fixed_point_qmax(int precision, int block, int K);
+
+hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block,
+                      hipStream_t st);
+hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st);
+hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st);
+hipError_t launch_zero(double *p, size_t n, hipStream_t st);
+// Fixed-order merge of part [B][Q] into final outputs.
+hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, const double *overflow,
+                        int n_opt, int G, const int *opt_orig, long long P, double spot,
+                        double *price, double *stderr_, double *grad, double *delta,
+                        hipStream_t st);
+hipError_t launch_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
+                               unsigned long long p0, long long n_paths, uint32_t *out,
+                               hipStream_t st);
+hipError_t launch_debug_normals(int precision, unsigned long long seed, unsigned long long p0,
+                                long long n_paths, int n_steps, double sqrt_dt_unused,
+                                void *out, hipStream_t st);
+
+}  // namespace lvk

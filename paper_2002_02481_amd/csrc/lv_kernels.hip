@@ -1,0 +1,826 @@
+// lv_kernels.hip -- gfx950 kernels for Monte Carlo pricing under the Dupire
+// local-volatility model and the adjoint of the price with respect to every node
+// of the vol grid (arXiv 2002.02481: the SDE and explicit Euler scheme of Sec.
+// IV-A, bilinear interpolation of Sec. IV-A/IV-D, payoff averages of Sec.
+// IV-B/IV-C, back-propagated sensitivities of Sec. III/IV-C).
+//
+// Mapping: one lane per path, 64-lane wavefronts, blocks of whole wavefronts that
+// loop over path tiles (persistent grid).  All lanes of a block are at the same
+// step, so the time cell of a step is uniform: each block stages, per window of
+// W steps, a table in LDS of the time-interpolated vol column and its
+// node-to-node difference, c[n][i] = sigma(x_i, t_n), d[n][i] = c[n][i+1] - c[n][i];
+// the spot lookup is then one 8- or 16-byte LDS read and one FMA.
+//
+// Gradient accumulation: per step a path adds x(1-f) to spot node i and x f to
+// node i+1 of that step's column (x = lambda * dy_{n+1}/dsigma_n), the time
+// weights being uniform.  LDS float atomics are slow on gfx950, integer ones are
+// not, so the two terms are rounded to fixed point (scale 2^F chosen from the
+// book's size) and added with ds_add_u32 (FP32 kernels) or ds_add_u64 (FP64
+// kernels) into a per-window histogram H[w][i][copy], privatised K ways by lane
+// to spread same-cell collisions.  At each window boundary the owner thread of
+// spot node i folds H into a per-block FP64 grid with the time weights; blocks
+// write their grids once and a fixed-order compensated merge combines them.
+// Terms too large for the fixed-point range take an FP64 global-atomic side path.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lv_internal.h"
+
+namespace lvk {
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies; the key advances by the Weyl constants between rounds.
+// --------------------------------------------------------------------------
+struct Words {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words{c0, c1, c2, c3};
+}
+
+// --------------------------------------------------------------------------
+// Per-precision arithmetic.  Uniforms are (2k+1) 2^-24 with k the top 23 bits of
+// a word: exact in float and double alike.
+// --------------------------------------------------------------------------
+template <typename R>
+struct Math;
+
+template <>
+struct Math<float> {
+    typedef int Acc;                       // fixed-point histogram word
+    static constexpr int FMAX = 40;
+    __device__ static __forceinline__ float uniform(uint32_t w) {
+        return fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+    }
+    // sqrt(dt) * (Z_a, Z_b) from one word pair (Box-Muller); the hardware sine
+    // and cosine take their argument in revolutions, i.e. compute sin(2 pi u).
+    __device__ static __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float sdt,
+                                                      float &za, float &zb) {
+        const float ua = uniform(wa), ub = uniform(wb);
+        const float r = __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(ua)) * sdt;
+        za = r * __builtin_amdgcn_cosf(ub);
+        zb = r * __builtin_amdgcn_sinf(ub);
+    }
+    __device__ static __forceinline__ float ex(float y) {
+        return __builtin_amdgcn_exp2f(y * 1.44269504f);
+    }
+    __device__ static __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static __forceinline__ Acc to_acc(float x) { return __float2int_rn(x); }
+    __device__ static __forceinline__ void acc_add(Acc *p, Acc v) { atomicAdd(p, v); }
+};
+
+template <>
+struct Math<double> {
+    typedef long long Acc;
+    static constexpr int FMAX = 62;
+    __device__ static __forceinline__ double uniform(uint32_t w) {
+        return fma((double)(w >> 9), 0x1p-23, 0x1p-24);
+    }
+    __device__ static __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double sdt,
+                                                      double &za, double &zb) {
+        const double ua = uniform(wa), ub = uniform(wb);
+        const double r = sqrt(-2.0 * log(ua)) * sdt;
+        double s, c;
+        sincospi(2.0 * ub, &s, &c);
+        za = r * c;
+        zb = r * s;
+    }
+    __device__ static __forceinline__ double ex(double y) { return exp(y); }
+    __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
+    __device__ static __forceinline__ Acc to_acc(double x) { return __double2ll_rn(x); }
+    __device__ static __forceinline__ void acc_add(Acc *p, Acc v) {
+        atomicAdd((unsigned long long *)p, (unsigned long long)v);
+    }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// --------------------------------------------------------------------------
+// LDS carve-up, shared by the kernels and the host planner.
+// --------------------------------------------------------------------------
+struct Lds {
+    size_t g64, wpart, wlam, tab, hist, total;
+};
+
+__host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes, int I, int J,
+                                          int n_opt, int wpb, int W, int K) {
+    Lds L{};
+    size_t off = 0;
+    const bool grad = variant == REV_STORED || variant == FUSED_CKPT;
+    const bool pay = variant != REV_STORED;
+    L.g64 = off;
+    off += grad ? align16((size_t)I * J * 8) : 0;
+    L.wpart = off;
+    off += pay ? align16((size_t)wpb * n_opt * 2 * 8) : 0;
+    L.wlam = off;
+    off += grad ? align16((size_t)wpb * 8) : 0;
+    L.tab = off;
+    off += align16((size_t)W * I * 2 * rbytes);
+    L.hist = off;
+    off += grad ? align16((size_t)W * I * K * accbytes) : 0;
+    L.total = off;
+    return L;
+}
+
+size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int K) {
+    const int rb = precision == 64 ? 8 : 4;
+    return lds_layout(variant, rb, rb, I, J, n_opt, block / 64, W, K).total;
+}
+
+__host__ __device__ double fixed_point_qmax(int precision, int block, int K) {
+    // FP32: every histogram word receives at most ceil(block/K) terms per window
+    // (one per path of its copy class) and must stay inside int32.  FP64: the K
+    // words of a node are summed in int64 at the fold, so the whole block's terms
+    // must fit.
+    if (precision == 64) return ldexp(1.0, 62) / block;
+    return floor(2147483000.0 / (double)((block + K - 1) / K)) - 2.0;
+}
+
+// --------------------------------------------------------------------------
+// Device building blocks
+// --------------------------------------------------------------------------
+// Table of steps n0 .. n0+nw-1: c = sigma(x_i, t_n), d = c(x_{i+1}) - c(x_i),
+// time-interpolated in FP64 and rounded once.
+template <typename R>
+__device__ void build_table(R *tab, const Args &a, int n0, int nw) {
+    const int I = a.I, J = a.J;
+    for (int e = threadIdx.x; e < nw * I; e += blockDim.x) {
+        const int w = e / I, i = e - w * I, n = n0 + w;
+        const int j = a.tj[n];
+        const double al = a.ta[n];
+        const double *s = a.sigma;
+        const double c0 = (1.0 - al) * s[i * J + j] + al * s[i * J + j + 1];
+        double c1 = c0;
+        if (i + 1 < I) c1 = (1.0 - al) * s[(i + 1) * J + j] + al * s[(i + 1) * J + j + 1];
+        tab[2 * e] = (R)c0;
+        tab[2 * e + 1] = (R)(c1 - c0);
+    }
+}
+
+template <typename R>
+struct Look {
+    R s;       // sigma(S_n, t_n)
+    R f;       // position inside the spot cell
+    R d;       // node difference of the cell (d sigma / d a)
+    R S;       // spot (linear axis only)
+    int i;     // lower spot node
+    bool in;   // strictly inside the spot range (slope is zero outside)
+};
+
+template <typename R, int AXIS>
+__device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off, R amax, int imax,
+                                          R spot) {
+    Look<R> L;
+    R x;
+    if (AXIS == 0) {
+        L.S = spot * Math<R>::ex(y);
+        x = L.S;
+    } else {
+        L.S = 0;
+        x = y;
+    }
+    const R a = fma(x, inv_du, a_off);
+    L.in = (a > (R)0) && (a < amax);
+    const R ac = fmin(fmax(a, (R)0), amax);
+    L.i = min((int)ac, imax);
+    L.f = ac - (R)L.i;
+    const R c = trow[2 * L.i], d = trow[2 * L.i + 1];
+    L.s = fma(L.f, d, c);
+    L.d = d;
+    return L;
+}
+
+// Forward payoff taps at step n+1 (the state is y_{n+1}): wave sums of payoff
+// and payoff^2 in FP64 into the wave's LDS slot.
+template <typename R>
+__device__ __forceinline__ void fwd_payoffs(const Args &a, int tap, R y, bool active, double *wpart,
+                                            int wave, int lane) {
+    const double S = (double)((R)a.spot * Math<R>::ex(y));
+    const int k0 = a.tap_first[tap], kc = a.tap_count[tap];
+    for (int q = 0; q < kc; ++q) {
+        const int k = k0 + q;
+        const double K = a.opt_strike[k];
+        double pay = a.opt_put[k] ? fmax(K - S, 0.0) : fmax(S - K, 0.0);
+        if (!active) pay = 0.0;
+        const double s1 = wave_sum(pay), s2 = wave_sum(pay * pay);
+        if (lane == 0) {
+            wpart[(wave * a.n_opt + k) * 2] += s1;
+            wpart[(wave * a.n_opt + k) * 2 + 1] += s2;
+        }
+    }
+}
+
+// Adjoint seeds at step n+1: lambda += sum_k w_k d payoff_k / d y.
+template <typename R>
+__device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam) {
+    const R S = (R)a.spot * Math<R>::ex(y);
+    const double Sd = (double)S;
+    const int k0 = a.tap_first[tap], kc = a.tap_count[tap];
+    for (int q = 0; q < kc; ++q) {
+        const int k = k0 + q;
+        const double K = a.opt_strike[k];
+        const R w = (R)a.cot[a.opt_orig[k]];
+        if (a.opt_put[k]) {
+            if (Sd < K) lam -= w * S;
+        } else {
+            if (Sd > K) lam += w * S;
+        }
+    }
+    return lam;
+}
+
+// Fold window histogram into the block grid: owner thread of spot node i.
+template <typename R>
+__device__ void fold(const Args &a, typename Math<R>::Acc *H, double *g64, int w0, int nw,
+                     double inv_sc) {
+    typedef typename Math<R>::Acc Acc;
+    const int I = a.I, J = a.J, K = a.K;
+    for (int i = threadIdx.x; i < I; i += blockDim.x) {
+        for (int w = 0; w < nw; ++w) {
+            Acc *h = H + (size_t)(w * I + i) * K;
+            long long s = 0;
+            for (int c = 0; c < K; ++c) {
+                s += (long long)h[c];
+                h[c] = 0;
+            }
+            if (s != 0) {
+                const int n = w0 + w;
+                const int j = a.tj[n];
+                const double al = a.ta[n];
+                const double v = (double)s * inv_sc;
+                g64[i * J + j] += (1.0 - al) * v;
+                g64[i * J + j + 1] += al * v;
+            }
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *H, int wn, int n,
+                                        const Look<R> &L, R gb, R sc, R qm, int copy) {
+    typedef typename Math<R>::Acc Acc;
+    const R x = gb * sc;
+    if (x == (R)0) return;
+    if (fabs(x) <= qm) {
+        const Acc q1 = Math<R>::to_acc(x * L.f);
+        const Acc q0 = Math<R>::to_acc(x) - q1;
+        Acc *h = H + ((size_t)(wn * a.I + L.i) * a.K + copy);
+        Math<R>::acc_add(h, q0);
+        Math<R>::acc_add(h + a.K, q1);
+    } else {
+        // rare: outside the fixed-point range (or not finite): FP64 global atomics
+        const int j = a.tj[n];
+        const double al = a.ta[n], g = (double)gb, f = (double)L.f;
+        const int J = a.J;
+        atomicAdd(&a.overflow[L.i * J + j], g * (1.0 - f) * (1.0 - al));
+        atomicAdd(&a.overflow[(L.i + 1) * J + j], g * f * (1.0 - al));
+        atomicAdd(&a.overflow[L.i * J + j + 1], g * (1.0 - f) * al);
+        atomicAdd(&a.overflow[(L.i + 1) * J + j + 1], g * f * al);
+    }
+}
+
+// Fixed-point exponent F from the book: terms are rarely above 8 * sum_k |w_k| max(S0, K_k).
+__device__ __forceinline__ int fixed_point_bits(const Args &a, double qmax, int fbits_max) {
+    double scale = 0.0;
+    for (int k = 0; k < a.n_opt; ++k)
+        scale += fabs(a.cot[a.opt_orig[k]]) * fmax(a.spot, a.opt_strike[k]);
+    if (!(scale > 0.0)) return fbits_max;
+    const int F = ilogb(qmax / (8.0 * scale));
+    return F < -30 ? -30 : (F > fbits_max ? fbits_max : F);
+}
+
+// --------------------------------------------------------------------------
+// Forward kernel: price-only, or storing every state (split / stored adjoint).
+// --------------------------------------------------------------------------
+template <typename R, int AXIS, bool STORE>
+__global__ void __launch_bounds__(1024) k_fwd(Args a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Lds lay = lds_layout(STORE ? FWD_STORE : FWD_PRICE, sizeof(R), sizeof(R), a.I, a.J,
+                               a.n_opt, wpb, a.W, a.K);
+    double *wpart = (double *)(smem + lay.wpart);
+    R *tab = (R *)(smem + lay.tab);
+    for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
+
+    const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
+    const R spot = (R)a.spot, amax = (R)(a.I - 1);
+    const int imax = a.I - 2, N = a.N, n_groups = (N + 3) >> 2;
+
+    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const long long p = (long long)tile * blockDim.x + tid;
+        const bool active = p < a.P;
+        R y = 0;
+        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1, wstart = 0;
+        for (int g = 0; g < n_groups; ++g) {
+            const int n0 = g << 2;
+            if (n0 % a.W == 0) {
+                __syncthreads();
+                build_table<R>(tab, a, n0, min(a.W, N - n0));
+                __syncthreads();
+                wstart = n0;
+            }
+            const Words w = philox10((uint32_t)g, 0u, (uint32_t)p, (uint32_t)((unsigned long long)p >> 32),
+                                     a.key0, a.key1);
+            R z[4];
+            Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
+            Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = n0 + r;
+                if (n < N) {
+                    const R *trow = tab + 2 * (n - wstart) * a.I;
+                    const Look<R> L = lookup<R, AXIS>(y, trow, inv_du, a_off, amax, imax, spot);
+                    y = fma(L.s, fma(-hdt, L.s, z[r]), y);
+                    if (STORE && active) ((R *)a.states)[(size_t)n * a.P + p] = y;
+                    if (n + 1 == next_tap) {
+                        fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
+                        ++tap;
+                        next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * a.n_opt; e += blockDim.x) {
+        double acc = 0.0;
+        for (int v = 0; v < wpb; ++v) acc += wpart[v * 2 * a.n_opt + e];
+        a.part[(size_t)blockIdx.x * a.Q + e] = acc;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Reverse kernel over stored states.  c_n = dy_{n+1}/dsigma_n = -sigma_n dt +
+// sqrt(dt) Z_n is recovered from the stored states as (y_{n+1} - y_n)/sigma_n
+// - sigma_n dt / 2, so no random numbers are drawn again.
+// --------------------------------------------------------------------------
+template <typename R, int AXIS>
+__global__ void __launch_bounds__(1024) k_rev(Args a) {
+    typedef typename Math<R>::Acc Acc;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int I = a.I, J = a.J, N = a.N, W = a.W, G = I * J;
+    const Lds lay = lds_layout(REV_STORED, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, W, a.K);
+    double *g64 = (double *)(smem + lay.g64);
+    double *wlam = (double *)(smem + lay.wlam);
+    R *tab = (R *)(smem + lay.tab);
+    Acc *H = (Acc *)(smem + lay.hist);
+    for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
+    for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
+    for (int e = tid; e < W * I * a.K; e += blockDim.x) H[e] = 0;
+
+    const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K);
+    const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
+    const R sc = (R)ldexp(1.0, F), qm = (R)qmax;
+    const double inv_sc = ldexp(1.0, -F);
+    const R hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
+    const R spot = (R)a.spot, amax = (R)(I - 1);
+    const int imax = I - 2, n_groups = (N + 3) >> 2, copy = tid % a.K;
+    const R *Y = (const R *)a.states;
+    const size_t P = (size_t)a.P;
+
+    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const long long p = (long long)tile * blockDim.x + tid;
+        const bool active = p < a.P;
+        R lam = 0;
+        R y_next = active ? Y[(size_t)(N - 1) * P + p] : (R)0;
+        int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+        int wcur = -1;
+        // cur[r] = y_{4g+r}; plane 4g+r-1; y_0 = 0
+        R cur[4], nxt[4];
+        {
+            const int g = n_groups - 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 4 * g + r;
+                cur[r] = (active && n >= 1 && n <= N - 1) ? Y[(size_t)(n - 1) * P + p] : (R)0;
+            }
+        }
+        for (int g = n_groups - 1; g >= 0; --g) {
+            const int n0 = g << 2, wi = n0 / W;
+            if (wi != wcur) {
+                __syncthreads();
+                if (wcur >= 0) fold<R>(a, H, g64, wcur * W, min(W, N - wcur * W), inv_sc);
+                build_table<R>(tab, a, wi * W, min(W, N - wi * W));
+                __syncthreads();
+                wcur = wi;
+            }
+            if (g > 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = 4 * (g - 1) + r;
+                    nxt[r] = (active && n >= 1) ? Y[(size_t)(n - 1) * P + p] : (R)0;
+                }
+            }
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int n = n0 + r;
+                if (n < N) {
+                    if (n + 1 == cur_tap) {
+                        lam = rev_seeds<R>(a, tap, y_next, lam);
+                        if (!active) lam = 0;
+                        --tap;
+                        cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+                    }
+                    const R yp = cur[r];
+                    const int wn = n - wi * W;
+                    const Look<R> L = lookup<R, AXIS>(yp, tab + 2 * wn * I, inv_du, a_off, amax, imax, spot);
+                    const R c = (y_next - yp) * Math<R>::rcp(L.s) - hdt * L.s;
+                    const R gb = lam * c;
+                    R dsdy = L.in ? L.d * inv_du : (R)0;
+                    if (AXIS == 0) dsdy *= L.S;
+                    lam = fma(lam * c, dsdy, lam);
+                    if (active) scatter<R>(a, H, wn, n, L, gb, sc, qm, copy);
+                    y_next = yp;
+                }
+            }
+            if (g > 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cur[r] = nxt[r];
+            }
+        }
+        __syncthreads();
+        fold<R>(a, H, g64, wcur * W, min(W, N - wcur * W), inv_sc);
+        const double l0 = wave_sum(active ? (double)lam : 0.0);
+        if (lane == 0) wlam[wave] += l0;
+    }
+    __syncthreads();
+    double *out = a.part + (size_t)blockIdx.x * a.Q;
+    if (tid == 0) {
+        double acc = 0.0;
+        for (int v = 0; v < wpb; ++v) acc += wlam[v];
+        out[2 * a.n_opt] = acc;
+    }
+    for (int e = tid; e < G; e += blockDim.x) out[2 * a.n_opt + 1 + e] = g64[e];
+}
+
+// --------------------------------------------------------------------------
+// Fused kernel with checkpoints: per path tile, a forward pass that keeps the
+// state at the start of every SEG-step segment and the payoff sums, then the
+// reverse pass segment by segment (last first): the segment is re-simulated
+// from its checkpoint with the same Philox counters, its states and
+// c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and swept backwards.
+// Checkpoints live in per-block slots reused by every tile of the block.
+// --------------------------------------------------------------------------
+template <typename R, int AXIS, int SEG>
+__global__ void __launch_bounds__(1024) k_fused(Args a) {
+    typedef typename Math<R>::Acc Acc;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int I = a.I, J = a.J, N = a.N, G = I * J;
+    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, a.K);
+    double *g64 = (double *)(smem + lay.g64);
+    double *wpart = (double *)(smem + lay.wpart);
+    double *wlam = (double *)(smem + lay.wlam);
+    R *tab = (R *)(smem + lay.tab);
+    Acc *H = (Acc *)(smem + lay.hist);
+    for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
+    for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
+    for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
+    for (int e = tid; e < SEG * I * a.K; e += blockDim.x) H[e] = 0;
+
+    const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K);
+    const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
+    const R sc = (R)ldexp(1.0, F), qm = (R)qmax;
+    const double inv_sc = ldexp(1.0, -F);
+    const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
+    const R spot = (R)a.spot, amax = (R)(I - 1);
+    const int imax = I - 2, n_seg = (N + SEG - 1) / SEG, copy = tid % a.K;
+    R *CK = (R *)a.ckpt;
+    const size_t slot_stride = (size_t)gridDim.x * blockDim.x;
+    const size_t slot = (size_t)blockIdx.x * blockDim.x + tid;
+
+    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const long long p = (long long)tile * blockDim.x + tid;
+        const bool active = p < a.P;
+        const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
+        // ---- forward: checkpoints and payoff sums
+        R y = 0;
+        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
+        for (int sg = 0; sg < n_seg; ++sg) {
+            const int na = sg * SEG, nw = min(SEG, N - na);
+            CK[(size_t)sg * slot_stride + slot] = y;
+            __syncthreads();
+            build_table<R>(tab, a, na, nw);
+            __syncthreads();
+#pragma unroll
+            for (int q4 = 0; q4 < SEG / 4; ++q4) {
+                const int n0 = na + 4 * q4;
+                if (n0 < N) {
+                    const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
+                    R z[4];
+                    Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
+                    Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = n0 + r;
+                        if (n < N) {
+                            const Look<R> L = lookup<R, AXIS>(y, tab + 2 * (4 * q4 + r) * I, inv_du,
+                                                              a_off, amax, imax, spot);
+                            y = fma(L.s, fma(-hdt, L.s, z[r]), y);
+                            if (n + 1 == next_tap) {
+                                fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
+                                ++tap;
+                                next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // ---- reverse, segment by segment
+        R lam = 0, y_next = y;
+        int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+        for (int sg = n_seg - 1; sg >= 0; --sg) {
+            const int na = sg * SEG, nw = min(SEG, N - na);
+            __syncthreads();
+            if (sg < n_seg - 1) fold<R>(a, H, g64, na + SEG, min(SEG, N - na - SEG), inv_sc);
+            build_table<R>(tab, a, na, nw);
+            __syncthreads();
+            R ys[SEG], cs[SEG];
+            R yy = CK[(size_t)sg * slot_stride + slot];
+#pragma unroll
+            for (int q4 = 0; q4 < SEG / 4; ++q4) {
+                const int n0 = na + 4 * q4;
+                if (n0 < N) {
+                    const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
+                    R z[4];
+                    Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
+                    Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 4 * q4 + r;
+                        if (n0 + r < N) {
+                            const Look<R> L = lookup<R, AXIS>(yy, tab + 2 * k * I, inv_du, a_off,
+                                                              amax, imax, spot);
+                            ys[k] = yy;
+                            cs[k] = fma((R)-2 * hdt, L.s, z[r]);
+                            yy = fma(L.s, fma(-hdt, L.s, z[r]), yy);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = SEG - 1; k >= 0; --k) {
+                const int n = na + k;
+                if (n < N) {
+                    if (n + 1 == cur_tap) {
+                        lam = rev_seeds<R>(a, rtap, y_next, lam);
+                        if (!active) lam = 0;
+                        --rtap;
+                        cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+                    }
+                    const R yp = ys[k];
+                    const Look<R> L = lookup<R, AXIS>(yp, tab + 2 * k * I, inv_du, a_off, amax, imax, spot);
+                    const R c = cs[k];
+                    const R gb = lam * c;
+                    R dsdy = L.in ? L.d * inv_du : (R)0;
+                    if (AXIS == 0) dsdy *= L.S;
+                    lam = fma(lam * c, dsdy, lam);
+                    if (active) scatter<R>(a, H, k, n, L, gb, sc, qm, copy);
+                    y_next = yp;
+                }
+            }
+        }
+        __syncthreads();
+        fold<R>(a, H, g64, 0, min(SEG, N), inv_sc);
+        const double l0 = wave_sum(active ? (double)lam : 0.0);
+        if (lane == 0) wlam[wave] += l0;
+    }
+    __syncthreads();
+    double *out = a.part + (size_t)blockIdx.x * a.Q;
+    for (int e = tid; e < 2 * a.n_opt; e += blockDim.x) {
+        double acc = 0.0;
+        for (int v = 0; v < wpb; ++v) acc += wpart[v * 2 * a.n_opt + e];
+        out[e] = acc;
+    }
+    if (tid == 0) {
+        double acc = 0.0;
+        for (int v = 0; v < wpb; ++v) acc += wlam[v];
+        out[2 * a.n_opt] = acc;
+    }
+    for (int e = tid; e < G; e += blockDim.x) out[2 * a.n_opt + 1 + e] = g64[e];
+}
+
+// --------------------------------------------------------------------------
+// Fixed-order merge: Neumaier sums over blocks in block order, two levels.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier(double &sum, double &comp, double x) {
+    const double t = sum + x;
+    if (fabs(sum) >= fabs(x))
+        comp += (sum - t) + x;
+    else
+        comp += (x - t) + sum;
+    sum = t;
+}
+
+__global__ void k_merge1(const double *part, int B, int Q, int S, double *seg) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (q >= Q) return;
+    const int b0 = (int)((long long)B * s / S), b1 = (int)((long long)B * (s + 1) / S);
+    double sum = 0.0, comp = 0.0;
+    for (int b = b0; b < b1; ++b) neumaier(sum, comp, part[(size_t)b * Q + q]);
+    seg[(size_t)s * Q + q] = sum + comp;
+}
+
+__device__ __forceinline__ double seg_total(const double *seg, int S, int Q, int q) {
+    double sum = 0.0, comp = 0.0;
+    for (int s = 0; s < S; ++s) neumaier(sum, comp, seg[(size_t)s * Q + q]);
+    return sum + comp;
+}
+
+__global__ void k_merge2(const double *seg, int S, int Q, const double *overflow, int n_opt, int G,
+                         const int *opt_orig, long long P, double spot, double *price,
+                         double *stderr_, double *grad, double *delta) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const double Pd = (double)P;
+    if (t < n_opt) {
+        const double s1 = seg_total(seg, S, Q, 2 * t), s2 = seg_total(seg, S, Q, 2 * t + 1);
+        const int o = opt_orig[t];
+        price[o] = s1 / Pd;
+        const double var = (s2 - s1 * s1 / Pd) / (Pd - 1.0);
+        stderr_[o] = sqrt(fmax(var, 0.0) / Pd);
+    } else if (t == n_opt) {
+        if (delta) *delta = seg_total(seg, S, Q, 2 * n_opt) / Pd / spot;
+    } else if (grad && t < n_opt + 1 + G) {
+        const int q = t - n_opt - 1;
+        grad[q] = (seg_total(seg, S, Q, 2 * n_opt + 1 + q) + overflow[q]) / Pd;
+    }
+}
+
+__global__ void k_zero(double *p, size_t n) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x)
+        p[e] = 0.0;
+}
+
+// --------------------------------------------------------------------------
+// Test-support kernels
+// --------------------------------------------------------------------------
+__global__ void k_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
+                               unsigned long long p0, long long n_paths, uint32_t *out) {
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= n_paths) return;
+    const unsigned long long p = p0 + (unsigned long long)q;
+    for (int mi = 0; mi < n_m; ++mi) {
+        const unsigned long long m = m0 + (unsigned long long)mi;
+        const Words w = philox10((uint32_t)m, (uint32_t)(m >> 32), (uint32_t)p, (uint32_t)(p >> 32),
+                                 (uint32_t)seed, (uint32_t)(seed >> 32));
+        uint32_t *o = out + ((size_t)q * n_m + mi) * 4;
+        o[0] = w.x;
+        o[1] = w.y;
+        o[2] = w.z;
+        o[3] = w.w;
+    }
+}
+
+template <typename R>
+__global__ void k_debug_normals(unsigned long long seed, unsigned long long p0, long long n_paths,
+                                int N, R *out) {
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= n_paths) return;
+    const unsigned long long p = p0 + (unsigned long long)q;
+    for (int g = 0; 4 * g < N; ++g) {
+        const Words w = philox10((uint32_t)g, 0u, (uint32_t)p, (uint32_t)(p >> 32), (uint32_t)seed,
+                                 (uint32_t)(seed >> 32));
+        R z[4];
+        Math<R>::box_muller(w.x, w.y, (R)1, z[0], z[1]);
+        Math<R>::box_muller(w.z, w.w, (R)1, z[2], z[3]);
+        for (int r = 0; r < 4 && 4 * g + r < N; ++r) out[(size_t)q * N + 4 * g + r] = z[r];
+    }
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+template <typename R>
+static size_t lds_of(int variant, const Args &a, int block, int W) {
+    const int rb = sizeof(R);
+    return lds_layout(variant, rb, rb, a.I, a.J, a.n_opt, block / 64, W, a.K).total;
+}
+
+hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block, hipStream_t st) {
+    const int v = store ? FWD_STORE : FWD_PRICE;
+    if (precision == 64) {
+        const size_t lds = lds_of<double>(v, a, block, a.W);
+        if (a.axis == 0) {
+            if (store) hipLaunchKernelGGL((k_fwd<double, 0, true>), dim3(blocks), dim3(block), lds, st, a);
+            else hipLaunchKernelGGL((k_fwd<double, 0, false>), dim3(blocks), dim3(block), lds, st, a);
+        } else {
+            if (store) hipLaunchKernelGGL((k_fwd<double, 1, true>), dim3(blocks), dim3(block), lds, st, a);
+            else hipLaunchKernelGGL((k_fwd<double, 1, false>), dim3(blocks), dim3(block), lds, st, a);
+        }
+    } else {
+        const size_t lds = lds_of<float>(v, a, block, a.W);
+        if (a.axis == 0) {
+            if (store) hipLaunchKernelGGL((k_fwd<float, 0, true>), dim3(blocks), dim3(block), lds, st, a);
+            else hipLaunchKernelGGL((k_fwd<float, 0, false>), dim3(blocks), dim3(block), lds, st, a);
+        } else {
+            if (store) hipLaunchKernelGGL((k_fwd<float, 1, true>), dim3(blocks), dim3(block), lds, st, a);
+            else hipLaunchKernelGGL((k_fwd<float, 1, false>), dim3(blocks), dim3(block), lds, st, a);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st) {
+    if (precision == 64) {
+        const size_t lds = lds_of<double>(REV_STORED, a, block, a.W);
+        if (a.axis == 0) hipLaunchKernelGGL((k_rev<double, 0>), dim3(blocks), dim3(block), lds, st, a);
+        else hipLaunchKernelGGL((k_rev<double, 1>), dim3(blocks), dim3(block), lds, st, a);
+    } else {
+        const size_t lds = lds_of<float>(REV_STORED, a, block, a.W);
+        if (a.axis == 0) hipLaunchKernelGGL((k_rev<float, 0>), dim3(blocks), dim3(block), lds, st, a);
+        else hipLaunchKernelGGL((k_rev<float, 1>), dim3(blocks), dim3(block), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int SEG>
+static void fused_seg(const Args &a, int blocks, int block, hipStream_t st) {
+    const size_t lds = lds_of<R>(FUSED_CKPT, a, block, SEG);
+    if (a.axis == 0) hipLaunchKernelGGL((k_fused<R, 0, SEG>), dim3(blocks), dim3(block), lds, st, a);
+    else hipLaunchKernelGGL((k_fused<R, 1, SEG>), dim3(blocks), dim3(block), lds, st, a);
+}
+
+template <typename R>
+static void fused_any(const Args &a, int blocks, int block, hipStream_t st) {
+    switch (a.seg) {
+        case 8: fused_seg<R, 8>(a, blocks, block, st); break;
+        case 16: fused_seg<R, 16>(a, blocks, block, st); break;
+        default: fused_seg<R, 32>(a, blocks, block, st); break;
+    }
+}
+
+hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st) {
+    if (precision == 64) fused_any<double>(a, blocks, block, st);
+    else fused_any<float>(a, blocks, block, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, const double *overflow,
+                        int n_opt, int G, const int *opt_orig, long long P, double spot,
+                        double *price, double *stderr_, double *grad, double *delta,
+                        hipStream_t st) {
+    const int Qm = grad ? Q : 2 * n_opt + 1;   // entries merged
+    hipLaunchKernelGGL(k_merge1, dim3((Qm + 255) / 256, S), dim3(256), 0, st, part, B, Q, S, seg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // k_merge2 reads seg with row stride Q; k_merge1 wrote rows of stride Q.
+    const int T = n_opt + 1 + (grad ? G : 0);
+    hipLaunchKernelGGL(k_merge2, dim3((T + 255) / 256), dim3(256), 0, st, seg, S, Q, overflow, n_opt,
+                       G, opt_orig, P, spot, price, stderr_, grad, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
+                               unsigned long long p0, long long n_paths, uint32_t *out,
+                               hipStream_t st) {
+    const int blocks = (int)((n_paths + 255) / 256);
+    hipLaunchKernelGGL(k_debug_philox, dim3(blocks), dim3(256), 0, st, seed, m0, n_m, p0, n_paths, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_normals(int precision, unsigned long long seed, unsigned long long p0,
+                                long long n_paths, int n_steps, double, void *out, hipStream_t st) {
+    const int blocks = (int)((n_paths + 255) / 256);
+    if (precision == 64)
+        hipLaunchKernelGGL((k_debug_normals<double>), dim3(blocks), dim3(256), 0, st, seed, p0, n_paths,
+                           n_steps, (double *)out);
+    else
+        hipLaunchKernelGGL((k_debug_normals<float>), dim3(blocks), dim3(256), 0, st, seed, p0, n_paths,
+                           n_steps, (float *)out);
+    return hipGetLastError();
+}
+
+}  // namespace lvk

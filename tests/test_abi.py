@@ -1,0 +1,91 @@
+"""C ABI checks that need no GPU: the library loads, exports every function that
+include/lvmc.h declares, and rejects bad requests on the host."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2002_02481_amd import _lib
+import paper_2002_02481_amd as lv
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_header_symbol(lib):
+    names = _lib.header_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in lvmc.h but not exported"
+    assert set(names) == set(_lib.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def _req(**kw):
+    s = W.small_surface()
+    args = dict(surface=s, spot=100.0, strikes=[100.0], maturities=[1.0], n_paths=1024, n_steps=52)
+    args.update(kw)
+    return args
+
+
+def test_check_accepts_valid_requests():
+    assert lv.check(**_req()) == _lib.LV_OK
+    b = W.book64()
+    assert lv.check(W.book_surface(0), 100.0, b.strike, b.maturity, 1 << 20, 156,
+                    is_put=b.is_put, weights=b.weight) == _lib.LV_OK
+    assert lv.check(**_req(), precision=64, adjoint="checkpoint", ckpt_every=8) == _lib.LV_OK
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(spot=-1.0), _lib.LV_ERR_ARG),
+    (dict(spot=float("nan")), _lib.LV_ERR_ARG),
+    (dict(strikes=[0.0]), _lib.LV_ERR_ARG),
+    (dict(maturities=[-1.0]), _lib.LV_ERR_ARG),
+    (dict(n_paths=1), _lib.LV_ERR_ARG),
+    (dict(n_steps=0), _lib.LV_ERR_ARG),
+    (dict(strikes=[100.0, 90.0], maturities=[1.0, 0.3]), _lib.LV_ERR_STEP),
+    (dict(precision=16), _lib.LV_ERR_ARG),
+    (dict(adjoint=7), _lib.LV_ERR_ARG),
+    (dict(ckpt_every=12), _lib.LV_ERR_ARG),
+    (dict(block=100), _lib.LV_ERR_ARG),
+    (dict(copies=17), _lib.LV_ERR_ARG),
+    (dict(strikes=np.full(300, 100.0), maturities=np.full(300, 1.0)), _lib.LV_ERR_UNSUPPORTED),
+])
+def test_check_rejects(kw, status):
+    assert lv.check(**_req(**kw)) == status
+
+
+def test_check_rejects_bad_grids():
+    s = W.small_surface()
+    bad = s.sigma.copy(); bad[3, 4] = -0.1
+    assert lv.check(bad, 100.0, [100.0], [1.0], 64, 52, spot_axis=s.spot_axis,
+                    time_axis=s.time_axis) == _lib.LV_ERR_GRID
+    bad[3, 4] = np.inf
+    assert lv.check(bad, 100.0, [100.0], [1.0], 64, 52, spot_axis=s.spot_axis,
+                    time_axis=s.time_axis) == _lib.LV_ERR_GRID
+    assert lv.check(s.sigma[:1], 100.0, [100.0], [1.0], 64, 52, spot_axis=(1, 0, 50.0, 200.0),
+                    time_axis=s.time_axis) == _lib.LV_ERR_GRID
+    assert lv.check(s.sigma, 100.0, [100.0], [1.0], 64, 52, spot_axis=(21, 1, 0.0, 200.0),
+                    time_axis=s.time_axis) == _lib.LV_ERR_GRID
+    assert lv.check(s.sigma, 100.0, [100.0], [1.0], 64, 52, spot_axis=(21, 0, 200.0, 50.0),
+                    time_axis=s.time_axis) == _lib.LV_ERR_GRID
+
+
+def test_error_message_is_set(lib):
+    s = W.small_surface()
+    lv.check(s, -1.0, [100.0], [1.0], 64, 52)
+    assert b"spot" in lib.lv_last_error(None)
+
+
+def test_states_bytes():
+    assert lv.states_bytes(32, 524288, 156) == 524288 * 156 * 4
+    assert lv.states_bytes(64, 1000, 13) == 1000 * 13 * 8
+    with pytest.raises(lv.LVError):
+        lv.states_bytes(16, 1000, 13)
+
+
+def test_null_context_is_rejected(lib):
+    st = lib.lv_price_and_grad(None, None, None, 100.0, None, 64, 52, 0, None, None, None, None, None)
+    assert st == _lib.LV_ERR_ARG

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same Philox streams.
+
+Bars (the FP32 path steps, interpolates and back-propagates in FP32 and sums
+across paths in FP64):
+  * Philox words: bit-exact.
+  * price: |GPU - oracle| < 1e-5 * spot; std_err within 1e-4 relative.
+  * gradient: every bucket within 1e-4 * max|g|; buckets the oracle leaves
+    exactly zero are exactly zero.
+  * the FP64 kernels: price within 1e-11 relative, buckets within 1e-9 * max|g|.
+The oracle sees the surface rounded to float32 when it checks the FP32 kernels,
+so that input rounding is not counted as error.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PRICE_TOL = 1e-5 * 100.0
+GRAD_TOL = 1e-4
+F64_PRICE_REL = 1e-11
+F64_GRAD = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lv():
+    import paper_2002_02481_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(lv):
+    return lv.Context(0)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.default()
+
+
+def gpu_run(lv, ctx, surface, book, n_paths, n_steps, seed=0, **opts):
+    say(f"  gpu: {surface.sigma.shape} P={n_paths} N={n_steps} opts={opts}")
+    p, s, g, d = lv.price_and_grad(surface, 100.0, book.strike, book.maturity, n_paths, n_steps,
+                                   seed, is_put=book.is_put, weights=book.weight, ctx=ctx, **opts)
+    return dict(price=p, stderr=s, grad=g, delta=d)
+
+
+def assert_parity(got, ref, precision=32, what=""):
+    gmax = np.abs(ref["grad"]).max() if ref.get("grad") is not None else 0.0
+    if precision == 32:
+        dp = np.abs(got["price"] - ref["price"]).max()
+        assert dp < PRICE_TOL, f"{what}: price differs by {dp}"
+        assert np.allclose(got["stderr"], ref["stderr"], rtol=1e-4, atol=1e-9), what
+        if got.get("grad") is not None:
+            dg = np.abs(got["grad"] - ref["grad"]).max()
+            say(f"  {what}: max|dprice|={dp:.3g} max|dgrad|/max|g|={dg / gmax:.3g}")
+            assert dg <= GRAD_TOL * gmax, f"{what}: bucket error {dg} vs max|g| {gmax}"
+            zero = ref["grad"] == 0.0
+            assert np.all(got["grad"][zero] == 0.0), f"{what}: zero buckets differ"
+    else:
+        rel = np.abs(got["price"] - ref["price"]) / np.maximum(np.abs(ref["price"]), 1e-300)
+        assert np.all(rel < F64_PRICE_REL), f"{what}: FP64 price rel err {rel.max()}"
+        assert np.allclose(got["stderr"], ref["stderr"], rtol=1e-9, atol=1e-15)
+        if got.get("grad") is not None:
+            dg = np.abs(got["grad"] - ref["grad"]).max()
+            say(f"  {what}: FP64 max|dgrad|/max|g|={dg / gmax:.3g}")
+            assert dg <= F64_GRAD * gmax
+            zero = ref["grad"] == 0.0
+            assert np.all(got["grad"][zero] == 0.0)
+    if got.get("delta") is not None and ref.get("delta") is not None:
+        tol = 1e-4 * max(1.0, abs(ref["delta"])) if precision == 32 else 1e-10 * max(1.0, abs(ref["delta"]))
+        assert abs(got["delta"] - ref["delta"]) < tol, f"{what}: delta {got['delta']} vs {ref['delta']}"
+
+
+# --------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------
+def test_philox_words_bit_exact(lv, ctx, orc):
+    import torch
+    for seed in (0, 0xDEADBEEFCAFEF00D):
+        p0, n_p, m0, n_m = 2**32 - 100, 256, 2**32 - 3, 8
+        say(f"  philox seed={seed:#x} p0={p0} m0={m0}")
+        out = torch.zeros(n_p * n_m * 4, dtype=torch.int32, device="cuda")
+        lv._check_status(ctx.lib.lv_debug_philox(ctx.h, seed, m0, n_m, p0, n_p,
+                                                  lv._ptr(out)), ctx.h)
+        got = out.cpu().numpy().view(np.uint32).reshape(n_p, n_m, 4)
+        ref = np.array([[orc.philox_words(seed, m0 + mi, p0 + q) for mi in range(n_m)]
+                        for q in range(n_p)], dtype=np.uint32)
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_normals(lv, ctx, orc, precision):
+    import torch
+    n_p, N = 512, 64
+    dt = torch.float32 if precision == 32 else torch.float64
+    out = torch.zeros(n_p * N, dtype=dt, device="cuda")
+    say(f"  normals precision={precision}")
+    lv._check_status(ctx.lib.lv_debug_normals(ctx.h, precision, 7, 1000, n_p, N, lv._ptr(out)), ctx.h)
+    got = out.cpu().double().numpy().reshape(n_p, N)
+    ref = orc.normals(7, 1000, n_p, N)
+    err = np.abs(got - ref) / (1.0 + np.abs(ref))
+    say(f"  normals precision={precision}: max rel err {err.max():.3g}")
+    assert err.max() < (2e-6 if precision == 32 else 1e-14)
+
+
+# --------------------------------------------------------------------------
+# pricing parity at sizes the oracle finishes quickly
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,adjoint", [(32, "stored"), (64, "stored"), (32, "checkpoint"),
+                                               (64, "checkpoint")])
+def test_small_call(lv, ctx, orc, precision, adjoint):
+    wl = W.small_call()
+    s = wl.surface.rounded_to_f32() if precision == 32 else wl.surface
+    ref = orc.price_and_grad(s, wl.book, wl.n_paths, wl.n_steps, wl.seed)
+    got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed,
+                  precision=precision, adjoint=adjoint)
+    assert_parity(got, ref, precision, f"small call {precision} {adjoint}")
+
+
+def test_price_only_matches(lv, ctx, orc):
+    wl = W.small_call()
+    ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps, want_grad=False)
+    p, s, g, d = lv.price_and_grad(wl.surface, 100.0, wl.book.strike, wl.book.maturity, wl.n_paths,
+                                   wl.n_steps, 0, adjoint="none", ctx=ctx)
+    assert g is None and d is None
+    assert abs(p[0] - ref["price"][0]) < PRICE_TOL
+
+
+def mixed_book():
+    return W.Book([0, 1, 0, 1, 0], [100.0, 95.0, 120.0, 80.0, 101.5], [3.0, 1.0, 0.5, 3.0, 2.0],
+                  [1.0, 2.0, -0.5, 1.5, 0.25])
+
+
+@pytest.mark.parametrize("precision,adjoint", [(32, "stored"), (64, "stored"), (32, "checkpoint")])
+def test_book_log_axis_ragged(lv, ctx, orc, precision, adjoint):
+    """Log-spaced 60 x 30 grid, calls and puts of uneven maturity with weights, a path
+    count that is not a multiple of the block and 156 steps (not a multiple of 16)."""
+    surf = W.book_surface(0)
+    book = mixed_book()
+    P, N = 20000 + 37, 156
+    s = surf.rounded_to_f32() if precision == 32 else surf
+    ref = orc.price_and_grad(s, book, P, N, seed=3)
+    got = gpu_run(lv, ctx, surf, book, P, N, 3, precision=precision, adjoint=adjoint)
+    assert_parity(got, ref, precision, f"book {precision} {adjoint}")
+
+
+@pytest.mark.parametrize("P,N", [(2, 1), (3, 2), (1000, 13), (257, 5)])
+def test_degenerate_shapes(lv, ctx, orc, P, N):
+    surf = W.tiny_surface(W.LIN, 5, 4, seed=1)
+    book = W.Book([0, 1], [100.0, 104.0], [1.0, 1.0], [1.0, -1.0])
+    for precision in (32, 64):
+        s = surf.rounded_to_f32() if precision == 32 else surf
+        ref = orc.price_and_grad(s, book, P, N, seed=11)
+        for adjoint in ("stored", "checkpoint"):
+            got = gpu_run(lv, ctx, surf, book, P, N, 11, precision=precision, adjoint=adjoint)
+            assert_parity(got, ref, precision, f"P={P} N={N} {precision} {adjoint}")
+
+
+def test_zero_buckets_exact(lv, ctx, orc):
+    sa = W.Axis(40, W.LIN, 10.0, 400.0)
+    ta = W.Axis(5, W.LIN, 0.0, 2.0)
+    rng = np.random.default_rng(2)
+    surf = W.Surface(sa, ta, rng.uniform(0.15, 0.3, (40, 5)))
+    book = W.call(100.0, 2.0 / 52)
+    for precision in (32, 64):
+        s = surf.rounded_to_f32() if precision == 32 else surf
+        ref = orc.price_and_grad(s, book, 4096, 2, seed=1)
+        got = gpu_run(lv, ctx, surf, book, 4096, 2, 1, precision=precision)
+        assert np.array_equal(got["grad"] == 0.0, ref["grad"] == 0.0)
+        assert_parity(got, ref, precision, f"zero buckets {precision}")
+
+
+def test_block_shapes_agree(lv, ctx, orc):
+    """Every launch shape computes the same thing: block sizes, histogram copies,
+    windows and grid sizes all pass the same parity bar."""
+    wl = W.small_call()
+    ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps)
+    for opts in [dict(block=64), dict(block=128, copies=1), dict(block=512, copies=16),
+                 dict(block=256, window=4), dict(block=256, window=32, blocks_per_cu=1),
+                 dict(block=1024, copies=4), dict(adjoint="checkpoint", ckpt_every=8),
+                 dict(adjoint="checkpoint", ckpt_every=32, block=128)]:
+        got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, **opts)
+        assert_parity(got, ref, 32, f"shape {opts}")
+
+
+# --------------------------------------------------------------------------
+# batched surfaces, device API, graphs, autograd
+# --------------------------------------------------------------------------
+def test_surface_batch(lv, ctx, orc):
+    surfs = [W.wide_surface(s) for s in (1, 2, 3)]
+    sig = np.stack([s.sigma for s in surfs])
+    book = W.call(100.0, 5.0)
+    P, N = 4096, 260
+    say("  batch of 3 wide surfaces, checkpoint")
+    p, se, g, d = lv.price_and_grad_batch(sig, 100.0, book.strike, book.maturity, P, N, 0,
+                                          spot_axis=surfs[0].spot_axis, time_axis=surfs[0].time_axis,
+                                          adjoint="checkpoint", ctx=ctx)
+    for k, s in enumerate(surfs):
+        ref = orc.price_and_grad(s.rounded_to_f32(), book, P, N)
+        assert_parity(dict(price=p[k], stderr=se[k], grad=g[k], delta=d[k]), ref, 32, f"batch surface {k}")
+
+
+def test_device_api_and_graph_replay(lv, ctx):
+    import torch
+    wl = W.small_call()
+    sig = torch.tensor(wl.surface.sigma, dtype=torch.float64, device="cuda")
+    kw = dict(spot_axis=wl.surface.spot_axis, time_axis=wl.surface.time_axis, ctx=ctx)
+    say("  eager device call")
+    eager = lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], wl.n_paths, wl.n_steps, 0, **kw)
+    eager = [t.clone() for t in eager]
+    torch.cuda.synchronize()
+    out = [torch.empty_like(t) for t in eager]
+    for rep in range(3):
+        say(f"  graph replay {rep}")
+        lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], wl.n_paths, wl.n_steps, 0, out=out,
+                              use_graph=True, **kw)
+        torch.cuda.synchronize()
+        assert ctx.run_info()["graph_replayed"] == (1 if rep > 0 else 0)
+        # prices are bit-stable; the gradient histogram is integer, so it is too
+        for a, b in zip(out, eager):
+            assert torch.equal(a, b)
+        # eager work between replays
+        lv.price_and_grad_dev(sig * 1.01, 100.0, [100.0], [1.0], 1024, wl.n_steps, 5, **kw)
+        torch.cuda.synchronize()
+
+
+def test_autograd_split_matches_fused(lv, ctx):
+    import torch
+    surf = W.book_surface(0)
+    book = mixed_book()
+    P, N = 8192 + 5, 156
+    sig = torch.tensor(surf.sigma, dtype=torch.float64, device="cuda", requires_grad=True)
+    spec = dict(spot=100.0, strikes=book.strike, maturities=book.maturity, is_put=book.is_put,
+                n_paths=P, n_steps=N, seed=9, spot_axis=surf.spot_axis, time_axis=surf.time_axis,
+                precision=32)
+    say("  LVPrice forward/backward")
+    price, stderr = lv.LVPrice.apply(sig, spec)
+    w = torch.tensor(book.weight, dtype=torch.float64, device="cuda")
+    (price * w).sum().backward()
+    p, s, g, d = lv.price_and_grad(surf, 100.0, book.strike, book.maturity, P, N, 9,
+                                   is_put=book.is_put, weights=book.weight, ctx=ctx)
+    assert np.allclose(price.detach().cpu().numpy(), p, rtol=0, atol=1e-12)
+    gmax = np.abs(g).max()
+    assert np.abs(sig.grad.cpu().numpy() - g).max() <= 1e-6 * gmax
+
+
+# --------------------------------------------------------------------------
+# full size, in the benchmark's launch configuration
+# --------------------------------------------------------------------------
+def test_full_size_single_call_60x30(lv, ctx, orc):
+    wl = W.single_call_60x30()
+    say(f"  full-size {wl.name}: GPU")
+    got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed)
+    info = ctx.run_info()
+    blocks = ctx.block_grads(wl.surface.sigma.size)
+    say(f"  full-size {wl.name}: oracle ({oracle.default_threads()} threads)")
+    ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps, wl.seed)
+    assert_parity(got, ref, 32, wl.name)
+    # sampled block partials: block b covered tiles b, b + B, ...
+    B, T = info["n_blocks"], info["tile_paths"]
+    n_tiles = (wl.n_paths + T - 1) // T
+    for b in (0, 1, B // 2, B - 1):
+        ranges = [(t * T, min((t + 1) * T, wl.n_paths)) for t in range(b, n_tiles, B)]
+        r = orc.sums(wl.surface.rounded_to_f32(), wl.book, wl.n_steps, wl.seed, ranges)
+        gb = blocks[b].reshape(wl.surface.sigma.shape)
+        scale = np.abs(r["sum_grad"]).max()
+        assert np.abs(gb - r["sum_grad"]).max() <= GRAD_TOL * scale, f"block {b}"
