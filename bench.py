@@ -129,9 +129,9 @@ def main():
                                        "max_bucket_err_vs_stored": float(np.abs(oc[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
         result["variants"] = variants
         result["accuracy"] = {
-            "fp32_vs_fp64_gpu_price_abs": float(abs(price32[0] - p64[0])),
+            "fp32_vs_fp64_gpu_price_abs": float(abs(price32.ravel()[0] - p64.ravel()[0])),
             "fp32_vs_fp64_gpu_max_bucket_err_rel_maxg": float(np.abs(grad32 - g64).max() / np.abs(g64).max()),
-            "price": float(price32[0]), "stderr": float(se32[0]),
+            "price": float(price32.ravel()[0]), "stderr": float(se32.ravel()[0]),
         }
 
     if not args.no_cpu:

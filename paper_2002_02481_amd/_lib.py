@@ -101,6 +101,10 @@ def load(path: str = LIBRARY):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run `python __graft_entry__.py` "
                            "(or paper_2002_02481_amd/build.py) first")
+    # Load PyTorch's HIP runtime first: the library then binds to that same
+    # runtime (same soname), so device pointers and streams are shared with torch
+    # and the process holds a single HIP runtime.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

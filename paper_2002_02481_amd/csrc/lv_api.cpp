@@ -232,8 +232,9 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     }
 
     // launch shape
-    pl.block = o.block ? o.block : 256;
-    pl.K = o.copies ? o.copies : 8;
+    // defaults from a launch-shape sweep of the 2^19 x 156, 60 x 30 workload
+    pl.block = o.block ? o.block : 512;
+    pl.K = o.copies ? o.copies : 4;
     pl.W = o.window ? o.window : 16;
     if (pl.adjoint == LV_ADJ_CHECKPOINT) pl.W = pl.seg;
     const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
@@ -242,9 +243,11 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
         size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, pl.block, pl.W, pl.K);
         return std::max(a, b);
     };
-    // shrink histogram copies, then the window, until the block fits in LDS
-    while (need() > max_lds && pl.K > 1 && !o.copies) pl.K /= 2;
-    while (need() > max_lds && pl.W > 4 && !o.window && pl.adjoint != LV_ADJ_CHECKPOINT) pl.W /= 2;
+    // shrink histogram copies, then the window, until the block fits in 64 KiB of
+    // LDS (several blocks per CU); beyond that use up to the CU's whole LDS
+    const size_t soft = std::min<size_t>(max_lds, 65536);
+    while (need() > soft && pl.K > 1 && !o.copies) pl.K /= 2;
+    while (need() > soft && pl.W > 4 && !o.window && pl.adjoint != LV_ADJ_CHECKPOINT) pl.W /= 2;
     if (need() > max_lds)
         return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)", need(), max_lds);
     pl.n_tiles = (int)((n_paths + pl.block - 1) / pl.block);
@@ -532,7 +535,7 @@ lv_status run_dev(lv_ctx *ctx, const Plan &pl, int n_surf, const double *sigmas_
 int device_cus(int device, size_t *max_lds) {
     hipDeviceProp_t pr;
     if (hipGetDeviceProperties(&pr, device) != hipSuccess) return 256;
-    if (max_lds) *max_lds = std::min<size_t>(pr.sharedMemPerBlock, 65536);
+    if (max_lds) *max_lds = std::min<size_t>(pr.sharedMemPerBlock, 160 * 1024);
     return pr.multiProcessorCount;
 }
 

@@ -435,28 +435,40 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
                     nxt[r] = (active && n >= 1) ? Y[(size_t)(n - 1) * P + p] : (R)0;
                 }
             }
+            // phase 1: lookups and dy_{n+1}/dsigma_n of the group's steps; they do not
+            // depend on lambda, so their LDS reads overlap instead of queueing behind
+            // the histogram atomics of the lambda chain
+            const int wn0 = n0 - wi * W;
+            Look<R> L[4];
+            R cc[4], dsd[4], yup[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (n0 + r < N) {
+                    yup[r] = (r == 3 || n0 + r + 1 >= N) ? y_next : cur[r + 1];
+                    L[r] = lookup<R, AXIS>(cur[r], tab + 2 * (wn0 + r) * I, inv_du, a_off, amax, imax, spot);
+                    cc[r] = (yup[r] - cur[r]) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
+                    R d = L[r].in ? L[r].d * inv_du : (R)0;
+                    if (AXIS == 0) d *= L[r].S;
+                    dsd[r] = d;
+                }
+            }
+            // phase 2: seeds, the lambda recursion and the histogram scatter
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int n = n0 + r;
                 if (n < N) {
                     if (n + 1 == cur_tap) {
-                        lam = rev_seeds<R>(a, tap, y_next, lam);
+                        lam = rev_seeds<R>(a, tap, yup[r], lam);
                         if (!active) lam = 0;
                         --tap;
                         cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
                     }
-                    const R yp = cur[r];
-                    const int wn = n - wi * W;
-                    const Look<R> L = lookup<R, AXIS>(yp, tab + 2 * wn * I, inv_du, a_off, amax, imax, spot);
-                    const R c = (y_next - yp) * Math<R>::rcp(L.s) - hdt * L.s;
-                    const R gb = lam * c;
-                    R dsdy = L.in ? L.d * inv_du : (R)0;
-                    if (AXIS == 0) dsdy *= L.S;
-                    lam = fma(lam * c, dsdy, lam);
-                    if (active) scatter<R>(a, H, wn, n, L, gb, sc, qm, copy);
-                    y_next = yp;
+                    const R gb = lam * cc[r];
+                    lam = fma(lam * cc[r], dsd[r], lam);
+                    if (active) scatter<R>(a, H, wn0 + r, n, L[r], gb, sc, qm, copy);
                 }
             }
+            y_next = cur[0];
             if (g > 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) cur[r] = nxt[r];
@@ -584,24 +596,37 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
                 }
             }
 #pragma unroll
-            for (int k = SEG - 1; k >= 0; --k) {
-                const int n = na + k;
-                if (n < N) {
-                    if (n + 1 == cur_tap) {
-                        lam = rev_seeds<R>(a, rtap, y_next, lam);
-                        if (!active) lam = 0;
-                        --rtap;
-                        cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+            for (int q4 = SEG / 4 - 1; q4 >= 0; --q4) {
+                // lookups of four steps first (independent of lambda), then the chain
+                Look<R> L[4];
+                R dsd[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 4 * q4 + r;
+                    if (na + k < N) {
+                        L[r] = lookup<R, AXIS>(ys[k], tab + 2 * k * I, inv_du, a_off, amax, imax, spot);
+                        R d = L[r].in ? L[r].d * inv_du : (R)0;
+                        if (AXIS == 0) d *= L[r].S;
+                        dsd[r] = d;
                     }
-                    const R yp = ys[k];
-                    const Look<R> L = lookup<R, AXIS>(yp, tab + 2 * k * I, inv_du, a_off, amax, imax, spot);
-                    const R c = cs[k];
-                    const R gb = lam * c;
-                    R dsdy = L.in ? L.d * inv_du : (R)0;
-                    if (AXIS == 0) dsdy *= L.S;
-                    lam = fma(lam * c, dsdy, lam);
-                    if (active) scatter<R>(a, H, k, n, L, gb, sc, qm, copy);
-                    y_next = yp;
+                }
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {
+                    const int k = 4 * q4 + r;
+                    const int n = na + k;
+                    if (n < N) {
+                        if (n + 1 == cur_tap) {
+                            lam = rev_seeds<R>(a, rtap, y_next, lam);
+                            if (!active) lam = 0;
+                            --rtap;
+                            cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+                        }
+                        const R c = cs[k];
+                        const R gb = lam * c;
+                        lam = fma(lam * c, dsd[r], lam);
+                        if (active) scatter<R>(a, H, k, n, L[r], gb, sc, qm, copy);
+                        y_next = ys[k];
+                    }
                 }
             }
         }
@@ -722,25 +747,38 @@ static size_t lds_of(int variant, const Args &a, int block, int W) {
     return lds_layout(variant, rb, rb, a.I, a.J, a.n_opt, block / 64, W, a.K).total;
 }
 
+// Blocks above 64 KiB of LDS (gfx950 has 160 KiB per CU) must be allowed per kernel.
+template <typename Kern>
+static void allow_lds(Kern kernel, size_t lds) {
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+#define LAUNCH(kern, blocks, block, lds, st, a)                                    \
+    do {                                                                           \
+        allow_lds(kern, lds);                                                      \
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(block), lds, st, a);           \
+    } while (0)
+
 hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block, hipStream_t st) {
     const int v = store ? FWD_STORE : FWD_PRICE;
     if (precision == 64) {
         const size_t lds = lds_of<double>(v, a, block, a.W);
         if (a.axis == 0) {
-            if (store) hipLaunchKernelGGL((k_fwd<double, 0, true>), dim3(blocks), dim3(block), lds, st, a);
-            else hipLaunchKernelGGL((k_fwd<double, 0, false>), dim3(blocks), dim3(block), lds, st, a);
+            if (store) LAUNCH((k_fwd<double, 0, true>), blocks, block, lds, st, a);
+            else LAUNCH((k_fwd<double, 0, false>), blocks, block, lds, st, a);
         } else {
-            if (store) hipLaunchKernelGGL((k_fwd<double, 1, true>), dim3(blocks), dim3(block), lds, st, a);
-            else hipLaunchKernelGGL((k_fwd<double, 1, false>), dim3(blocks), dim3(block), lds, st, a);
+            if (store) LAUNCH((k_fwd<double, 1, true>), blocks, block, lds, st, a);
+            else LAUNCH((k_fwd<double, 1, false>), blocks, block, lds, st, a);
         }
     } else {
         const size_t lds = lds_of<float>(v, a, block, a.W);
         if (a.axis == 0) {
-            if (store) hipLaunchKernelGGL((k_fwd<float, 0, true>), dim3(blocks), dim3(block), lds, st, a);
-            else hipLaunchKernelGGL((k_fwd<float, 0, false>), dim3(blocks), dim3(block), lds, st, a);
+            if (store) LAUNCH((k_fwd<float, 0, true>), blocks, block, lds, st, a);
+            else LAUNCH((k_fwd<float, 0, false>), blocks, block, lds, st, a);
         } else {
-            if (store) hipLaunchKernelGGL((k_fwd<float, 1, true>), dim3(blocks), dim3(block), lds, st, a);
-            else hipLaunchKernelGGL((k_fwd<float, 1, false>), dim3(blocks), dim3(block), lds, st, a);
+            if (store) LAUNCH((k_fwd<float, 1, true>), blocks, block, lds, st, a);
+            else LAUNCH((k_fwd<float, 1, false>), blocks, block, lds, st, a);
         }
     }
     return hipGetLastError();
@@ -749,12 +787,12 @@ hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int 
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st) {
     if (precision == 64) {
         const size_t lds = lds_of<double>(REV_STORED, a, block, a.W);
-        if (a.axis == 0) hipLaunchKernelGGL((k_rev<double, 0>), dim3(blocks), dim3(block), lds, st, a);
-        else hipLaunchKernelGGL((k_rev<double, 1>), dim3(blocks), dim3(block), lds, st, a);
+        if (a.axis == 0) LAUNCH((k_rev<double, 0>), blocks, block, lds, st, a);
+        else LAUNCH((k_rev<double, 1>), blocks, block, lds, st, a);
     } else {
         const size_t lds = lds_of<float>(REV_STORED, a, block, a.W);
-        if (a.axis == 0) hipLaunchKernelGGL((k_rev<float, 0>), dim3(blocks), dim3(block), lds, st, a);
-        else hipLaunchKernelGGL((k_rev<float, 1>), dim3(blocks), dim3(block), lds, st, a);
+        if (a.axis == 0) LAUNCH((k_rev<float, 0>), blocks, block, lds, st, a);
+        else LAUNCH((k_rev<float, 1>), blocks, block, lds, st, a);
     }
     return hipGetLastError();
 }
@@ -762,8 +800,8 @@ hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipSt
 template <typename R, int SEG>
 static void fused_seg(const Args &a, int blocks, int block, hipStream_t st) {
     const size_t lds = lds_of<R>(FUSED_CKPT, a, block, SEG);
-    if (a.axis == 0) hipLaunchKernelGGL((k_fused<R, 0, SEG>), dim3(blocks), dim3(block), lds, st, a);
-    else hipLaunchKernelGGL((k_fused<R, 1, SEG>), dim3(blocks), dim3(block), lds, st, a);
+    if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG>), blocks, block, lds, st, a);
+    else LAUNCH((k_fused<R, 1, SEG>), blocks, block, lds, st, a);
 }
 
 template <typename R>

