@@ -28,9 +28,25 @@ PEAK_VALU_TOPS = PEAK_FP32_TFLOPS / 2.0   # 256 CUs x 128 FP32 lanes/clk x 2.4 G
 # Algorithmic work per path-step ("Roofline"): VALU lane-operations
 # of the method's arithmetic, and HBM bytes of the stored states.
 OPS_FWD = 34.0      # Philox/4 (15) + uniforms (3) + Box-Muller (4) + lookup (9) + Euler (2) + store (1)
-OPS_REV = 30.0      # load (1) + lookup (9) + dy/dsigma (3) + adjoint (5) + fixed-point scatter (12)
+OPS_REV = 32.0      # load (1) + lookup (9) + dy/dsigma (4) + slope (4) + adjoint (2) + scatter (12)
 BYTES_FWD = 4.0     # one FP32 state written per path-step
 BYTES_REV = 4.0     # one FP32 state read per path-step
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_call_60x30.json")
+    src = os.path.join(ROOT, "paper_2002_02481_amd", "csrc", "lv_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def parse():
@@ -40,11 +56,28 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64/forward/checkpoint variants")
+    ap.add_argument("--launch", default="", metavar="BLOCK,COPIES,WINDOW,BPC",
+                    help="fix the launch shape instead of autotuning it")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 4}), flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); "
               "the path shards by Philox path range, see DESIGN.md", file=sys.stderr)
@@ -64,11 +97,24 @@ def main():
     kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, ctx=ctx)
     strikes, mats = wl.book.strike, wl.book.maturity
 
-    def run(out=None, **opts):
+    def base_run(out=None, **opts):
         return lv.price_and_grad_dev(sig, 100.0, strikes, mats, P, N, wl.seed, out=out, **kw, **opts)
 
-    out = [t for t in run()]
+    if args.launch:
+        bl, k, w, c = (int(x) for x in args.launch.split(","))
+        out = [t for t in base_run(block=bl, copies=k, window=w, blocks_per_cu=c)]
+    else:
+        out = [t for t in base_run(autotune=True)]      # first call tunes the launch shape
     torch.cuda.synchronize()
+    info = ctx.run_info()
+    shape = dict(block=info["block"], copies=info["copies"], window=info["window"],
+                 blocks_per_cu=info["blocks_per_cu"])
+
+    def run(out=None, **opts):
+        for k, v in shape.items():
+            opts.setdefault(k, v)
+        return base_run(out=out, **opts)
+
     for _ in range(args.warmup):
         run(out=out, profile=True)
     torch.cuda.synchronize()
@@ -93,8 +139,10 @@ def main():
     achieved_tops = ops / (avg[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved_tops, 3),
                 "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "frac": round(achieved_tops / PEAK_VALU_TOPS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(dom),
+                "ops_per_path_step": OPS_FWD if dom == "fwd" else OPS_REV,
                 "hbm_achieved_GBs": round(byts / (avg[dom] * 1e-3) / 1e9, 1),
+                "hbm_frac": round(byts / (avg[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                 "avg_ms": {k: round(v, 5) for k, v in avg.items() if v}}
 
     price32, se32, grad32, delta32 = [t.cpu().numpy().copy() for t in out]
@@ -105,18 +153,18 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded 60x30 local-vol surface, Philox streams)",
         "config": {"workload": wl.name, "paths": P, "steps": N, "grid": list(s.sigma.shape),
-                   "options": 1, "adjoint": "stored", "parallelism": "none"},
+                   "options": 1, "adjoint": "stored", "parallelism": "none", "launch": shape},
         "roofline": roofline,
     }
 
     if not args.no_variants:
         variants = {}
         def timed(n, **opts):
-            o = [t for t in run(**opts)]
+            o = [t for t in base_run(autotune=True, **opts)]     # tunes this variant's shape
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(n):
-                run(out=o, **opts)
+                base_run(out=o, autotune=True, **opts)
             torch.cuda.synchronize()
             return (time.perf_counter() - t0) * 1e3 / n, o
         ms64, o64 = timed(max(3, args.steps // 4), precision=64)

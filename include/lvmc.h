@@ -105,6 +105,9 @@ typedef struct {
     int32_t window;         /* steps per LDS table/histogram window (multiple of 4); 0 = default */
     int32_t profile;        /* 1: time every kernel with hipEvents (eager launches only), read back
                                with lv_kernel_times */
+    int32_t autotune;       /* 1: on the first call of a shape (grid, steps, paths, book size,
+                               precision, adjoint), time every candidate launch shape that the
+                               fields above leave free and keep the fastest for this context */
 } lv_opts;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`
@@ -198,8 +201,20 @@ typedef struct {
     int32_t adjoint;
     int32_t precision;
     int32_t graph_replayed;     /* 1 if the last call replayed a captured graph */
+    int32_t copies;             /* histogram copies of the launch */
+    int32_t window;             /* steps per LDS window (the segment for the checkpoint kernel) */
+    int32_t blocks_per_cu;      /* persistent blocks per CU asked for */
+    int32_t autotuned;          /* 1 if the shape came from the autotuner */
     int64_t overflow_terms;     /* reserved: 0 */
 } lv_run_info;
+
+/* The launch shapes the autotuner would time for this request, as rows of
+ * (block, copies, window, blocks_per_cu) in shapes_out (host int32 [max][4]);
+ * *n_out receives the number of rows written.  Host only (device 0's
+ * properties are read when a device is present, else 256 CUs are assumed). */
+lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t n_paths,
+                               int32_t n_steps, const lv_opts *opts, int32_t *shapes_out,
+                               int32_t max, int32_t *n_out);
 
 lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info);
 

@@ -75,10 +75,25 @@ class _Book:
 
 
 def make_opts(precision=32, adjoint="stored", ckpt_every=16, use_graph=False, block=0,
-              blocks_per_cu=0, copies=0, window=0, profile=False) -> lv_opts:
+              blocks_per_cu=0, copies=0, window=0, profile=False, autotune=False) -> lv_opts:
     adj = ADJOINT[adjoint] if isinstance(adjoint, str) else int(adjoint)
     return lv_opts(int(precision), adj, int(ckpt_every), int(bool(use_graph)), int(block),
-                   int(blocks_per_cu), int(copies), int(window), int(bool(profile)))
+                   int(blocks_per_cu), int(copies), int(window), int(bool(profile)),
+                   int(bool(autotune)))
+
+
+def tuning_candidates(surface, strikes, maturities, n_paths, n_steps, *, is_put=None,
+                      spot_axis=None, time_axis=None, **opts):
+    """Launch shapes (block, copies, window, blocks_per_cu) the autotuner would time."""
+    grid, _ = _surface_parts(surface, spot_axis, time_axis)
+    book = _Book(strikes, maturities, is_put, None)
+    o = make_opts(**opts)
+    out = np.zeros((512, 4), dtype=np.int32)
+    n = C.c_int32()
+    _check_status(_lib_handle().lv_tuning_candidates(C.byref(grid), C.byref(book.c), int(n_paths),
+                                                     int(n_steps), C.byref(o), out.ctypes.data,
+                                                     512, C.byref(n)))
+    return [tuple(int(v) for v in row) for row in out[:n.value]]
 
 
 def _surface_parts(surface, spot_axis, time_axis):

@@ -41,14 +41,16 @@ class lv_book(C.Structure):
 class lv_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("adjoint", C.c_int32), ("ckpt_every", C.c_int32),
                 ("use_graph", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("copies", C.c_int32), ("window", C.c_int32), ("profile", C.c_int32)]
+                ("copies", C.c_int32), ("window", C.c_int32), ("profile", C.c_int32),
+                ("autotune", C.c_int32)]
 
 
 class lv_run_info(C.Structure):
     _fields_ = [("n_blocks", C.c_int32), ("block", C.c_int32), ("tile_paths", C.c_int32),
                 ("waves_per_block", C.c_int32), ("fixed_point_bits", C.c_int32),
                 ("adjoint", C.c_int32), ("precision", C.c_int32), ("graph_replayed", C.c_int32),
-                ("overflow_terms", C.c_int64)]
+                ("copies", C.c_int32), ("window", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("autotuned", C.c_int32), ("overflow_terms", C.c_int64)]
 
 
 class LVError(RuntimeError):
@@ -82,6 +84,7 @@ SIGNATURES = {
     "lv_last_run_info": (C.c_int, [_vp, C.POINTER(lv_run_info)]),
     "lv_debug_block_grads": (C.c_int, [_vp, _vp, C.c_size_t]),
     "lv_kernel_times": (C.c_int, [_vp, _vp, _vp, _i32]),
+    "lv_tuning_candidates": (C.c_int, [_PG, _PB, _i64, _i32, _PO, _vp, _i32, C.POINTER(C.c_int32)]),
 }
 
 

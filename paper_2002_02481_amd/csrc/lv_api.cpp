@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,11 @@ struct Buf {
     size_t n = 0;
 };
 
+// Launch shape: threads per block, histogram copies, window (steps), blocks per CU.
+struct Shape {
+    int block = 512, K = 2, W = 16, bpc = 2;
+};
+
 // Everything derived from one request: the time table, the book in maturity
 // order, the launch shape.
 struct Plan {
@@ -34,8 +40,10 @@ struct Plan {
     std::vector<int> tj, tap_step, tap_first, tap_count, opt_put, opt_orig;
     std::vector<double> ta, opt_strike, weight;
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;
-    int block = 256, blocks = 0, n_tiles = 0, W = 16, K = 8, S = 32;
+    int block = 256, blocks = 0, n_tiles = 0, W = 16, K = 8, S = 32, bpc = 2;
     int G = 0, Q = 0;
+    Shape user;            // caller-fixed shape fields (0 = free)
+    bool autotune = false;
 };
 
 }  // namespace
@@ -51,6 +59,9 @@ struct lv_ctx {
     std::vector<char> plan_bytes;     // what planbuf holds
     lv_run_info info{};
     int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
+    bool overflow_dirty = false;                 // a call stopped between adjoint and merge
+    std::map<std::string, Shape> tuned;          // autotuner results per request shape
+    bool last_autotuned = false;
     // kernel timing (lv_opts.profile)
     struct Timed {
         hipEvent_t a, b;
@@ -109,6 +120,81 @@ lv_status ensure(lv_ctx *ctx, Buf &b, size_t bytes) {
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// ---------------------------------------------------------------------------
+// Launch shapes
+// ---------------------------------------------------------------------------
+int floor_pow2(long long x) {
+    int p = 1;
+    while ((long long)p * 2 <= x) p *= 2;
+    return p;
+}
+
+size_t lds_need(const Plan &pl, const Shape &sh) {
+    const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
+    const int W = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W;
+    size_t a = lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, W, sh.K);
+    size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, W, sh.K);
+    return std::max(a, b);
+}
+
+// Defaults from launch-shape sweeps on MI355X: 1024-lane blocks with 2 histogram
+// copies and 32-step windows when there are enough paths for a block per CU;
+// smaller blocks for smaller problems so that every CU gets work.
+Shape default_shape(const Plan &pl, int n_cu) {
+    Shape sh;
+    sh.block = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(pl.P / n_cu)));
+    sh.K = 2;
+    sh.W = 32;
+    sh.bpc = 2;
+    return sh;
+}
+
+// Fix a shape into the plan, shrinking the window, then the copies (unless the
+// caller fixed them) until a block fits in 64 KiB of LDS (several blocks per CU);
+// beyond that up to the CU's whole LDS.
+lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds, bool may_shrink_k,
+                      bool may_shrink_w) {
+    const size_t soft = std::min<size_t>(max_lds, 65536);
+    while (lds_need(pl, sh) > soft && sh.W > 8 && may_shrink_w && pl.adjoint != LV_ADJ_CHECKPOINT) sh.W /= 2;
+    while (lds_need(pl, sh) > soft && sh.K > 1 && may_shrink_k) sh.K /= 2;
+    while (lds_need(pl, sh) > soft && sh.W > 4 && may_shrink_w && pl.adjoint != LV_ADJ_CHECKPOINT) sh.W /= 2;
+    if (lds_need(pl, sh) > max_lds)
+        return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)",
+                    lds_need(pl, sh), max_lds);
+    pl.block = sh.block;
+    pl.K = sh.K;
+    pl.W = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W;
+    pl.bpc = sh.bpc;
+    pl.n_tiles = (int)((pl.P + pl.block - 1) / pl.block);
+    pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * sh.bpc);
+    pl.S = std::min(64, pl.blocks);
+    return LV_OK;
+}
+
+// Candidate shapes the autotuner times (every one is a valid launch).
+std::vector<Shape> tuning_candidates(const Plan &pl, int n_cu, size_t max_lds) {
+    std::vector<Shape> out;
+    const int bmax = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(2 * pl.P / n_cu)));
+    const int blocks[] = {128, 256, 512, 1024};
+    const int ks[] = {1, 2, 4};
+    const int ws[] = {8, 16, 32};
+    const int bpcs[] = {1, 2, 4};
+    for (int b : blocks) {
+        if (b > bmax && b != 128) continue;
+        for (int k : ks)
+            for (int w : ws) {
+                if (pl.adjoint == LV_ADJ_CHECKPOINT && w != 8) continue;   // window = segment
+                for (int c : bpcs) {
+                    Shape sh{b, k, w, c};
+                    if (lds_need(pl, sh) > std::min<size_t>(max_lds, 65536)) continue;
+                    out.push_back(sh);
+                }
+            }
+    }
+    if (out.empty()) out.push_back(default_shape(pl, n_cu));
+    return out;
+}
 
 // ---------------------------------------------------------------------------
 // Validation and planning (host only, no GPU access)
@@ -231,34 +317,25 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
         pl.ta[n] = b - j;
     }
 
-    // launch shape
-    // defaults from a launch-shape sweep of the 2^19 x 156, 60 x 30 workload
-    pl.block = o.block ? o.block : 512;
-    pl.K = o.copies ? o.copies : 4;
-    pl.W = o.window ? o.window : 16;
-    if (pl.adjoint == LV_ADJ_CHECKPOINT) pl.W = pl.seg;
-    const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
-    auto need = [&]() {
-        size_t a = lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, pl.block, pl.W, pl.K);
-        size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, pl.block, pl.W, pl.K);
-        return std::max(a, b);
-    };
-    // shrink histogram copies, then the window, until the block fits in 64 KiB of
-    // LDS (several blocks per CU); beyond that use up to the CU's whole LDS
-    const size_t soft = std::min<size_t>(max_lds, 65536);
-    while (need() > soft && pl.K > 1 && !o.copies) pl.K /= 2;
-    while (need() > soft && pl.W > 4 && !o.window && pl.adjoint != LV_ADJ_CHECKPOINT) pl.W /= 2;
-    if (need() > max_lds)
-        return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)", need(), max_lds);
-    pl.n_tiles = (int)((n_paths + pl.block - 1) / pl.block);
-    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
-    pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * bpc);
-    pl.S = std::min(32, pl.blocks);
-    return LV_OK;
+    // launch shape: explicit options win; otherwise the tuned shape (autotune)
+    // or the default heuristics
+    pl.user.block = o.block;
+    pl.user.K = o.copies;
+    pl.user.W = o.window;
+    pl.user.bpc = o.blocks_per_cu;
+    pl.autotune = o.autotune != 0;
+    if (o.copies && (o.copies & (o.copies - 1)))
+        return fail(ctx, LV_ERR_ARG, "copies must be a power of two");
+    Shape sh = default_shape(pl, n_cu);
+    if (o.block) sh.block = o.block;
+    if (o.copies) sh.K = o.copies;
+    if (o.window) sh.W = o.window;
+    if (o.blocks_per_cu) sh.bpc = o.blocks_per_cu;
+    return apply_shape(ctx, pl, sh, n_cu, max_lds, !o.copies, !o.window);
 }
 
 int host_fixed_point_bits(const Plan &pl) {
-    const double qmax = lvk::fixed_point_qmax(pl.precision, pl.block, pl.K);
+    const double qmax = lvk::fixed_point_qmax(pl.precision, pl.block, pl.K, pl.P);
     double scale = 0.0;
     for (int q = 0; q < pl.n_opt; ++q)
         scale += std::fabs(pl.weight[pl.opt_orig[q]]) * std::max(pl.spot, pl.opt_strike[q]);
@@ -355,7 +432,14 @@ lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
     lv_status st;
     if ((st = ensure(ctx, ctx->part, (size_t)pl.blocks * pl.Q * 8)) != LV_OK) return st;
     if ((st = ensure(ctx, ctx->seg, (size_t)pl.S * pl.Q * 8)) != LV_OK) return st;
+    const size_t had = ctx->overflow.n;
     if ((st = ensure(ctx, ctx->overflow, (size_t)pl.G * 8)) != LV_OK) return st;
+    if (ctx->overflow.n != had || ctx->overflow_dirty) {
+        // the merge clears what it reads, so the side grid only needs zeroing when new
+        hipError_t e = lvk::launch_zero((double *)ctx->overflow.p, ctx->overflow.n / 8, ctx->stream());
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "zero fill: %s", hipGetErrorString(e));
+        ctx->overflow_dirty = false;
+    }
     if (adjoint && pl.adjoint == LV_ADJ_STORED) {
         const size_t b = (size_t)pl.N * (size_t)pl.P * real_bytes(pl.precision);
         if ((st = ensure(ctx, ctx->states, b)) != LV_OK) return st;
@@ -431,8 +515,7 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
                                      nullptr, st);
         });
     }
-    e = timed(ctx, prof, LV_K_ZERO, [&] { return lvk::launch_zero(a.overflow, pl.G, st); });
-    if (e != hipSuccess) return e;
+    ctx->overflow_dirty = true;
     if (pl.adjoint == LV_ADJ_STORED) {
         e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st); });
         if (e != hipSuccess) return e;
@@ -442,10 +525,12 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
         e = timed(ctx, prof, LV_K_FUSED, [&] { return lvk::launch_fused_ckpt(a, pl.precision, pl.blocks, pl.block, st); });
         if (e != hipSuccess) return e;
     }
-    return timed(ctx, prof, LV_K_MERGE, [&] {
+    e = timed(ctx, prof, LV_K_MERGE, [&] {
         return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
                                  pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, grad, delta, st);
     });
+    if (e == hipSuccess && grad) ctx->overflow_dirty = false;
+    return e;
 }
 
 void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
@@ -460,6 +545,10 @@ void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
     ctx->info.adjoint = adjoint ? pl.adjoint : LV_ADJ_NONE;
     ctx->info.precision = pl.precision;
     ctx->info.graph_replayed = replayed ? 1 : 0;
+    ctx->info.copies = pl.K;
+    ctx->info.window = pl.W;
+    ctx->info.blocks_per_cu = pl.bpc;
+    ctx->info.autotuned = ctx->last_autotuned ? 1 : 0;
     ctx->info.overflow_terms = 0;
 }
 
@@ -478,10 +567,81 @@ std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf
     return k;
 }
 
-lv_status run_dev(lv_ctx *ctx, const Plan &pl, int n_surf, const double *sigmas_dev,
+std::string tune_key(const Plan &pl, bool adjoint) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N, pl.axis,
+             pl.P, pl.precision, adjoint ? pl.adjoint : LV_ADJ_NONE, pl.seg, pl.n_opt, pl.n_taps,
+             pl.user.block, pl.user.K, pl.user.W, pl.user.bpc, (int)pl.profile);
+    return buf;
+}
+
+lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
+                  bool adjoint, bool use_graph, double *prices, double *stderrs, double *grads,
+                  double *deltas);
+
+// Time every candidate shape the caller left free on the first surface and keep
+// the fastest (per context and request shape).
+lv_status autotune(lv_ctx *ctx, Plan &pl, const double *sigmas_dev, bool adjoint, double *prices,
+                   double *stderrs, double *grads, double *deltas) {
+    const std::string key = tune_key(pl, adjoint);
+    auto it = ctx->tuned.find(key);
+    if (it == ctx->tuned.end()) {
+        std::vector<Shape> cands;
+        for (const Shape &c : tuning_candidates(pl, ctx->n_cu, ctx->max_lds)) {
+            if ((pl.user.block && c.block != pl.user.block) || (pl.user.K && c.K != pl.user.K) ||
+                (pl.user.W && c.W != pl.user.W) || (pl.user.bpc && c.bpc != pl.user.bpc))
+                continue;
+            cands.push_back(c);
+        }
+        if (cands.empty()) cands.push_back(Shape{pl.block, pl.K, pl.W, pl.bpc});
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHECK(ctx, hipEventCreate(&e0));
+        HIPCHECK(ctx, hipEventCreate(&e1));
+        Shape best = cands[0];
+        float best_ms = 1e30f;
+        lv_status st = LV_OK;
+        for (const Shape &c : cands) {
+            Plan q = pl;
+            q.autotune = false;
+            q.profile = 0;
+            if ((st = apply_shape(ctx, q, c, ctx->n_cu, ctx->max_lds, false, false)) != LV_OK) break;
+            // one untimed run (allocations, first-touch), then two timed runs
+            if ((st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas)) != LV_OK) break;
+            hipError_t e = hipEventRecord(e0, ctx->stream());
+            for (int r = 0; r < 2 && st == LV_OK; ++r)
+                st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas);
+            if (st != LV_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream());
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = fail(ctx, LV_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != LV_OK) return st;
+        it = ctx->tuned.emplace(key, best).first;
+    }
+    return apply_shape(ctx, pl, it->second, ctx->n_cu, ctx->max_lds, false, false);
+}
+
+lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
                   bool adjoint, bool use_graph, double *prices, double *stderrs, double *grads,
                   double *deltas) {
     lv_status s;
+    ctx->last_autotuned = false;
+    if (pl.autotune) {
+        if ((s = autotune(ctx, pl, sigmas_dev, adjoint, prices, stderrs, grads, deltas)) != LV_OK) return s;
+        pl.autotune = false;
+        ctx->last_autotuned = true;
+    }
     Tables t;
     if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
     if ((s = ensure_workspace(ctx, pl, adjoint)) != LV_OK) return s;
@@ -725,7 +885,6 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     Tables t;
     if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
     if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
-    // the reverse writes no payoff sums: the merge reads zeros there
     if ((s = ensure(ctx, ctx->out_stage, (size_t)2 * pl.n_opt * 8)) != LV_OK) return s;
     hipStream_t st = ctx->stream();
     lvk::Args a = make_args(pl, t, sigma_dev);
@@ -733,15 +892,16 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     a.overflow = (double *)ctx->overflow.p;
     a.states = const_cast<void *>(states_dev);
     a.cot = cotangent_dev;
-    hipError_t e = lvk::launch_zero(a.part, (size_t)pl.blocks * pl.Q, st);
-    if (e == hipSuccess) e = lvk::launch_zero(a.overflow, pl.G, st);
-    if (e == hipSuccess) e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
+    // the reverse writes no payoff sums: the merge's price outputs go to scratch
+    ctx->overflow_dirty = true;
+    hipError_t e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
     double *scratch = (double *)ctx->out_stage.p;
     if (e == hipSuccess)
         e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
                               pl.G, t.opt_orig, pl.P, pl.spot, scratch, scratch + pl.n_opt, grad_dev,
                               delta_dev, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    ctx->overflow_dirty = false;
     record_info(ctx, pl, true, false);
     ctx->info.fixed_point_bits = -1000;   // depends on the device cotangent
     return LV_OK;
@@ -781,6 +941,32 @@ lv_status lv_kernel_times(lv_ctx *ctx, double *ms, int64_t *counts, int32_t rese
             ctx->k_count[k] = 0;
         }
     }
+    return LV_OK;
+}
+
+lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t n_paths,
+                               int32_t n_steps, const lv_opts *opts, int32_t *shapes_out,
+                               int32_t max, int32_t *n_out) {
+    if (!shapes_out || !n_out || max < 1) return fail(nullptr, LV_ERR_ARG, "shapes_out, n_out and max >= 1 required");
+    int n_cu = 256;
+    size_t max_lds = 160 * 1024;
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) == hipSuccess && nd > 0) n_cu = device_cus(0, &max_lds);
+    else (void)hipGetLastError();
+    Plan pl;
+    lv_status s = plan_request(nullptr, grid, 1, nullptr, 100.0, book, n_paths, n_steps, 0, opts, n_cu,
+                               max_lds, pl);
+    if (s != LV_OK) return s;
+    int n = 0;
+    for (const Shape &c : tuning_candidates(pl, n_cu, max_lds)) {
+        if (n >= max) break;
+        shapes_out[4 * n + 0] = c.block;
+        shapes_out[4 * n + 1] = c.K;
+        shapes_out[4 * n + 2] = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : c.W;
+        shapes_out[4 * n + 3] = c.bpc;
+        ++n;
+    }
+    *n_out = n;
     return LV_OK;
 }
 

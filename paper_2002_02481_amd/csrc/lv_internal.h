@@ -49,15 +49,15 @@ enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };
 // LDS bytes a kernel variant needs for the given shape.
 size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int K);
 // Largest fixed-point term the gradient histogram accepts, for the given shape.
-__host__ __device__ double fixed_point_qmax(int precision, int block, int K);
+__host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P);
 
 hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block,
                       hipStream_t st);
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_zero(double *p, size_t n, hipStream_t st);
-// Fixed-order merge of part [B][Q] into final outputs.
-hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, const double *overflow,
+// Fixed-order merge of part [B][Q] into final outputs; reads and clears overflow.
+hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, double *overflow,
                         int n_opt, int G, const int *opt_orig, long long P, double spot,
                         double *price, double *stderr_, double *grad, double *delta,
                         hipStream_t st);

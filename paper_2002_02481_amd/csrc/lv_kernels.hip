@@ -25,6 +25,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lv_internal.h"
 
 namespace lvk {
@@ -122,7 +124,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 // LDS carve-up, shared by the kernels and the host planner.
 // --------------------------------------------------------------------------
 struct Lds {
-    size_t g64, wpart, wlam, tab, hist, total;
+    size_t g64, wpart, wlam, fbuf, tab, hist, total;
 };
 
 __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes, int I, int J,
@@ -137,6 +139,8 @@ __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes,
     off += pay ? align16((size_t)wpb * n_opt * 2 * 8) : 0;
     L.wlam = off;
     off += grad ? align16((size_t)wpb * 8) : 0;
+    L.fbuf = off;
+    off += grad ? align16((size_t)W * I * 8) : 0;
     L.tab = off;
     off += align16((size_t)W * I * 2 * rbytes);
     L.hist = off;
@@ -150,13 +154,14 @@ size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block,
     return lds_layout(variant, rb, rb, I, J, n_opt, block / 64, W, K).total;
 }
 
-__host__ __device__ double fixed_point_qmax(int precision, int block, int K) {
-    // FP32: every histogram word receives at most ceil(block/K) terms per window
-    // (one per path of its copy class) and must stay inside int32.  FP64: the K
-    // words of a node are summed in int64 at the fold, so the whole block's terms
-    // must fit.
-    if (precision == 64) return ldexp(1.0, 62) / block;
-    return floor(2147483000.0 / (double)((block + K - 1) / K)) - 2.0;
+__host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P) {
+    // Lanes with a path: at most min(block, P).  FP32: every histogram word receives
+    // at most one term per path of its copy class per window and must stay inside
+    // int32.  FP64: the K words of a node are summed in int64 at the fold, so all of
+    // a block's terms must fit.
+    const int act = (int)(P < block ? P : block);
+    if (precision == 64) return ldexp(1.0, 62) / act;
+    return floor(2147483000.0 / (double)((act + K - 1) / K)) - 2.0;
 }
 
 // --------------------------------------------------------------------------
@@ -179,6 +184,11 @@ __device__ void build_table(R *tab, const Args &a, int n0, int nw) {
         tab[2 * e + 1] = (R)(c1 - c0);
     }
 }
+
+__device__ __forceinline__ float clamp_to(float a, float hi) {
+    return __builtin_amdgcn_fmed3f(a, 0.0f, hi);
+}
+__device__ __forceinline__ double clamp_to(double a, double hi) { return fmin(fmax(a, 0.0), hi); }
 
 template <typename R>
 struct Look {
@@ -204,7 +214,7 @@ __device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off,
     }
     const R a = fma(x, inv_du, a_off);
     L.in = (a > (R)0) && (a < amax);
-    const R ac = fmin(fmax(a, (R)0), amax);
+    const R ac = clamp_to(a, amax);
     L.i = min((int)ac, imax);
     L.f = ac - (R)L.i;
     const R c = trow[2 * L.i], d = trow[2 * L.i + 1];
@@ -252,42 +262,62 @@ __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam) {
     return lam;
 }
 
-// Fold window histogram into the block grid: owner thread of spot node i.
+// Fold of a window's histogram into the block's FP64 grid, in two stages.
+// Stage 1 (all threads): F[w][i] = sum over copies of H[w][i][.] * 2^-F, H cleared.
 template <typename R>
-__device__ void fold(const Args &a, typename Math<R>::Acc *H, double *g64, int w0, int nw,
-                     double inv_sc) {
-    typedef typename Math<R>::Acc Acc;
-    const int I = a.I, J = a.J, K = a.K;
+__device__ void fold1(const Args &a, typename Math<R>::Acc *H, double *Fb, int nw, double inv_sc) {
+    const int I = a.I, K = a.K;
+    for (int e = threadIdx.x; e < nw * I; e += blockDim.x) {
+        typename Math<R>::Acc *h = H + (size_t)e * K;
+        long long s = 0;
+        for (int c = 0; c < K; ++c) {
+            s += (long long)h[c];
+            h[c] = 0;
+        }
+        Fb[e] = (double)s * inv_sc;
+    }
+}
+
+// Stage 2 (owner thread of spot node i): spread F[w][i] over time nodes j_w and
+// j_w + 1 with weights 1 - alpha_w and alpha_w, holding runs of equal j in registers.
+__device__ void fold2(const Args &a, const double *Fb, double *g64, int w0, int nw) {
+    const int I = a.I, J = a.J;
     for (int i = threadIdx.x; i < I; i += blockDim.x) {
+        int jc = -1;
+        double a0 = 0.0, a1 = 0.0;
         for (int w = 0; w < nw; ++w) {
-            Acc *h = H + (size_t)(w * I + i) * K;
-            long long s = 0;
-            for (int c = 0; c < K; ++c) {
-                s += (long long)h[c];
-                h[c] = 0;
+            const int n = w0 + w, j = a.tj[n];
+            const double al = a.ta[n], v = Fb[w * I + i];
+            if (j != jc) {
+                if (jc >= 0) {
+                    g64[i * J + jc] += a0;
+                    g64[i * J + jc + 1] += a1;
+                }
+                jc = j;
+                a0 = a1 = 0.0;
             }
-            if (s != 0) {
-                const int n = w0 + w;
-                const int j = a.tj[n];
-                const double al = a.ta[n];
-                const double v = (double)s * inv_sc;
-                g64[i * J + j] += (1.0 - al) * v;
-                g64[i * J + j + 1] += al * v;
-            }
+            a0 += (1.0 - al) * v;
+            a1 += al * v;
+        }
+        if (jc >= 0) {
+            g64[i * J + jc] += a0;
+            g64[i * J + jc + 1] += a1;
         }
     }
 }
 
+// Scatter of one step's adjoint term x = gb * 2^F: x(1-f) to node i and x f to
+// node i+1 of window row wn, in this lane's copy column Hl (= H + lane copy).
 template <typename R>
-__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *H, int wn, int n,
-                                        const Look<R> &L, R gb, R sc, R qm, int copy) {
+__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl, int wn, int n,
+                                        const Look<R> &L, R gb, R sc, R qm) {
     typedef typename Math<R>::Acc Acc;
     const R x = gb * sc;
     if (x == (R)0) return;
     if (fabs(x) <= qm) {
         const Acc q1 = Math<R>::to_acc(x * L.f);
         const Acc q0 = Math<R>::to_acc(x) - q1;
-        Acc *h = H + ((size_t)(wn * a.I + L.i) * a.K + copy);
+        Acc *h = Hl + __umul24((unsigned)(wn * a.I + L.i), (unsigned)a.K);
         Math<R>::acc_add(h, q0);
         Math<R>::acc_add(h + a.K, q1);
     } else {
@@ -375,7 +405,9 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
 // --------------------------------------------------------------------------
 // Reverse kernel over stored states.  c_n = dy_{n+1}/dsigma_n = -sigma_n dt +
 // sqrt(dt) Z_n is recovered from the stored states as (y_{n+1} - y_n)/sigma_n
-// - sigma_n dt / 2, so no random numbers are drawn again.
+// - sigma_n dt / 2, so no random numbers are drawn again.  Steps run in groups
+// of four: the four lookups first (they do not depend on lambda, so their LDS
+// reads overlap), then the lambda recursion and the histogram scatter.
 // --------------------------------------------------------------------------
 template <typename R, int AXIS>
 __global__ void __launch_bounds__(1024) k_rev(Args a) {
@@ -386,44 +418,51 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
     const Lds lay = lds_layout(REV_STORED, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, W, a.K);
     double *g64 = (double *)(smem + lay.g64);
     double *wlam = (double *)(smem + lay.wlam);
+    double *Fb = (double *)(smem + lay.fbuf);
     R *tab = (R *)(smem + lay.tab);
     Acc *H = (Acc *)(smem + lay.hist);
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < W * I * a.K; e += blockDim.x) H[e] = 0;
 
-    const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K);
+    const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K, a.P);
     const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
     const R sc = (R)ldexp(1.0, F), qm = (R)qmax;
     const double inv_sc = ldexp(1.0, -F);
     const R hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
     const R spot = (R)a.spot, amax = (R)(I - 1);
-    const int imax = I - 2, n_groups = (N + 3) >> 2, copy = tid % a.K;
+    const int imax = I - 2, n_groups = (N + 3) >> 2, K = a.K;
+    Acc *Hl = H + tid % K;               // this lane's copy column
     const R *Y = (const R *)a.states;
     const size_t P = (size_t)a.P;
 
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const long long p = (long long)tile * blockDim.x + tid;
         const bool active = p < a.P;
+        const size_t pc = active ? (size_t)p : P - 1;     // inactive lanes read a valid path
         R lam = 0;
-        R y_next = active ? Y[(size_t)(N - 1) * P + p] : (R)0;
+        R y_next = Y[(size_t)(N - 1) * P + pc];
         int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
         int wcur = -1;
-        // cur[r] = y_{4g+r}; plane 4g+r-1; y_0 = 0
+        // cur[r] = y_{4g+r} (plane 4g+r-1; y_0 = 0)
         R cur[4], nxt[4];
         {
             const int g = n_groups - 1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int n = 4 * g + r;
-                cur[r] = (active && n >= 1 && n <= N - 1) ? Y[(size_t)(n - 1) * P + p] : (R)0;
+                cur[r] = (n >= 1 && n <= N - 1) ? Y[(size_t)(n - 1) * P + pc] : (R)0;
             }
         }
         for (int g = n_groups - 1; g >= 0; --g) {
             const int n0 = g << 2, wi = n0 / W;
             if (wi != wcur) {
                 __syncthreads();
-                if (wcur >= 0) fold<R>(a, H, g64, wcur * W, min(W, N - wcur * W), inv_sc);
+                if (wcur >= 0) {
+                    fold1<R>(a, H, Fb, min(W, N - wcur * W), inv_sc);
+                    __syncthreads();
+                    fold2(a, Fb, g64, wcur * W, min(W, N - wcur * W));
+                }
                 build_table<R>(tab, a, wi * W, min(W, N - wi * W));
                 __syncthreads();
                 wcur = wi;
@@ -432,42 +471,46 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int n = 4 * (g - 1) + r;
-                    nxt[r] = (active && n >= 1) ? Y[(size_t)(n - 1) * P + p] : (R)0;
+                    nxt[r] = n >= 1 ? Y[(size_t)(n - 1) * P + pc] : (R)0;
                 }
             }
-            // phase 1: lookups and dy_{n+1}/dsigma_n of the group's steps; they do not
-            // depend on lambda, so their LDS reads overlap instead of queueing behind
-            // the histogram atomics of the lambda chain
             const int wn0 = n0 - wi * W;
-            Look<R> L[4];
-            R cc[4], dsd[4], yup[4];
+            auto group = [&](auto full_tag) {
+                constexpr bool FULL = decltype(full_tag)::value;
+                Look<R> L[4];
+                R cc[4], dsd[4], yup[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (n0 + r < N) {
-                    yup[r] = (r == 3 || n0 + r + 1 >= N) ? y_next : cur[r + 1];
-                    L[r] = lookup<R, AXIS>(cur[r], tab + 2 * (wn0 + r) * I, inv_du, a_off, amax, imax, spot);
-                    cc[r] = (yup[r] - cur[r]) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
-                    R d = L[r].in ? L[r].d * inv_du : (R)0;
-                    if (AXIS == 0) d *= L[r].S;
-                    dsd[r] = d;
-                }
-            }
-            // phase 2: seeds, the lambda recursion and the histogram scatter
-#pragma unroll
-            for (int r = 3; r >= 0; --r) {
-                const int n = n0 + r;
-                if (n < N) {
-                    if (n + 1 == cur_tap) {
-                        lam = rev_seeds<R>(a, tap, yup[r], lam);
-                        if (!active) lam = 0;
-                        --tap;
-                        cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+                for (int r = 0; r < 4; ++r) {
+                    if (FULL || n0 + r < N) {
+                        yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : cur[r + 1];
+                        L[r] = lookup<R, AXIS>(cur[r], tab + 2 * (wn0 + r) * I, inv_du, a_off, amax,
+                                               imax, spot);
+                        cc[r] = (yup[r] - cur[r]) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
+                        R d = L[r].in ? L[r].d * inv_du : (R)0;
+                        if (AXIS == 0) d *= L[r].S;
+                        dsd[r] = d;
                     }
-                    const R gb = lam * cc[r];
-                    lam = fma(lam * cc[r], dsd[r], lam);
-                    if (active) scatter<R>(a, H, wn0 + r, n, L[r], gb, sc, qm, copy);
                 }
-            }
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {
+                    const int n = n0 + r;
+                    if (FULL || n < N) {
+                        if (n + 1 == cur_tap) {
+                            lam = rev_seeds<R>(a, tap, yup[r], lam);
+                            if (!active) lam = 0;
+                            --tap;
+                            cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+                        }
+                        const R gb = lam * cc[r];
+                        lam = fma(lam * cc[r], dsd[r], lam);
+                        scatter<R>(a, Hl, wn0 + r, n, L[r], gb, sc, qm);
+                    }
+                }
+            };
+            if (n0 + 4 <= N)
+                group(std::true_type{});
+            else
+                group(std::false_type{});
             y_next = cur[0];
             if (g > 0) {
 #pragma unroll
@@ -475,7 +518,9 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
             }
         }
         __syncthreads();
-        fold<R>(a, H, g64, wcur * W, min(W, N - wcur * W), inv_sc);
+        fold1<R>(a, H, Fb, min(W, N - wcur * W), inv_sc);
+        __syncthreads();
+        fold2(a, Fb, g64, wcur * W, min(W, N - wcur * W));
         const double l0 = wave_sum(active ? (double)lam : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
@@ -507,6 +552,7 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
     double *g64 = (double *)(smem + lay.g64);
     double *wpart = (double *)(smem + lay.wpart);
     double *wlam = (double *)(smem + lay.wlam);
+    double *Fb = (double *)(smem + lay.fbuf);
     R *tab = (R *)(smem + lay.tab);
     Acc *H = (Acc *)(smem + lay.hist);
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
@@ -514,13 +560,14 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
     for (int e = tid; e < SEG * I * a.K; e += blockDim.x) H[e] = 0;
 
-    const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K);
+    const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K, a.P);
     const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
     const R sc = (R)ldexp(1.0, F), qm = (R)qmax;
     const double inv_sc = ldexp(1.0, -F);
     const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
     const R spot = (R)a.spot, amax = (R)(I - 1);
-    const int imax = I - 2, n_seg = (N + SEG - 1) / SEG, copy = tid % a.K;
+    const int imax = I - 2, n_seg = (N + SEG - 1) / SEG;
+    Acc *Hl = H + tid % a.K;
     R *CK = (R *)a.ckpt;
     const size_t slot_stride = (size_t)gridDim.x * blockDim.x;
     const size_t slot = (size_t)blockIdx.x * blockDim.x + tid;
@@ -569,7 +616,11 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
         for (int sg = n_seg - 1; sg >= 0; --sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
             __syncthreads();
-            if (sg < n_seg - 1) fold<R>(a, H, g64, na + SEG, min(SEG, N - na - SEG), inv_sc);
+            if (sg < n_seg - 1) {
+                fold1<R>(a, H, Fb, min(SEG, N - na - SEG), inv_sc);
+                __syncthreads();
+                fold2(a, Fb, g64, na + SEG, min(SEG, N - na - SEG));
+            }
             build_table<R>(tab, a, na, nw);
             __syncthreads();
             R ys[SEG], cs[SEG];
@@ -624,14 +675,16 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
                         const R c = cs[k];
                         const R gb = lam * c;
                         lam = fma(lam * c, dsd[r], lam);
-                        if (active) scatter<R>(a, H, k, n, L[r], gb, sc, qm, copy);
+                        scatter<R>(a, Hl, k, n, L[r], gb, sc, qm);
                         y_next = ys[k];
                     }
                 }
             }
         }
         __syncthreads();
-        fold<R>(a, H, g64, 0, min(SEG, N), inv_sc);
+        fold1<R>(a, H, Fb, min(SEG, N), inv_sc);
+        __syncthreads();
+        fold2(a, Fb, g64, 0, min(SEG, N));
         const double l0 = wave_sum(active ? (double)lam : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
@@ -662,22 +715,42 @@ __device__ __forceinline__ void neumaier(double &sum, double &comp, double x) {
     sum = t;
 }
 
+// Level 1: thread (q, s) sums blocks [B s / S, B (s+1) / S) of entry q in block
+// order; loads are issued in batches of 8 before the compensated adds.
 __global__ void k_merge1(const double *part, int B, int Q, int S, double *seg) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
     if (q >= Q) return;
     const int b0 = (int)((long long)B * s / S), b1 = (int)((long long)B * (s + 1) / S);
     double sum = 0.0, comp = 0.0;
-    for (int b = b0; b < b1; ++b) neumaier(sum, comp, part[(size_t)b * Q + q]);
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = part[(size_t)(b + k) * Q + q];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) neumaier(sum, comp, v[k]);
+    }
+    for (; b < b1; ++b) neumaier(sum, comp, part[(size_t)b * Q + q]);
     seg[(size_t)s * Q + q] = sum + comp;
 }
 
 __device__ __forceinline__ double seg_total(const double *seg, int S, int Q, int q) {
     double sum = 0.0, comp = 0.0;
-    for (int s = 0; s < S; ++s) neumaier(sum, comp, seg[(size_t)s * Q + q]);
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = seg[(size_t)(s + k) * Q + q];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) neumaier(sum, comp, v[k]);
+    }
+    for (; s < S; ++s) neumaier(sum, comp, seg[(size_t)s * Q + q]);
     return sum + comp;
 }
 
-__global__ void k_merge2(const double *seg, int S, int Q, const double *overflow, int n_opt, int G,
+// Level 2 and finalisation.  The rare-term FP64 side grid is read and cleared
+// here, so it is zero again for the next call.
+__global__ void k_merge2(const double *seg, int S, int Q, double *overflow, int n_opt, int G,
                          const int *opt_orig, long long P, double spot, double *price,
                          double *stderr_, double *grad, double *delta) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -693,6 +766,7 @@ __global__ void k_merge2(const double *seg, int S, int Q, const double *overflow
     } else if (grad && t < n_opt + 1 + G) {
         const int q = t - n_opt - 1;
         grad[q] = (seg_total(seg, S, Q, 2 * n_opt + 1 + q) + overflow[q]) / Pd;
+        overflow[q] = 0.0;
     }
 }
 
@@ -826,7 +900,7 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, const double *overflow,
+hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, double *overflow,
                         int n_opt, int G, const int *opt_orig, long long P, double spot,
                         double *price, double *stderr_, double *grad, double *delta,
                         hipStream_t st) {

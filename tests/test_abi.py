@@ -89,3 +89,23 @@ def test_states_bytes():
 def test_null_context_is_rejected(lib):
     st = lib.lv_price_and_grad(None, None, None, 100.0, None, 64, 52, 0, None, None, None, None, None)
     assert st == _lib.LV_ERR_ARG
+
+
+def test_tuning_candidates_are_valid_shapes():
+    s = W.book_surface(0)
+    for adjoint in ("stored", "checkpoint"):
+        c = lv.tuning_candidates(s, [100.0], [3.0], 524288, 156, adjoint=adjoint)
+        assert len(c) >= 4
+        for block, K, win, bpc in c:
+            assert block % 64 == 0 and 64 <= block <= 1024
+            assert K in (1, 2, 4) and bpc in (1, 2, 4)
+            assert win % 4 == 0
+        if adjoint == "checkpoint":
+            assert all(w == 16 for _, _, w, _ in c)
+    # fixed fields of the request restrict nothing here: the candidate grid is the tuner's
+    small = lv.tuning_candidates(W.small_surface(), [100.0], [1.0], 16384, 52)
+    assert all(b <= 128 for b, _, _, _ in small)
+
+
+def test_copies_must_be_power_of_two():
+    assert lv.check(**_req(), copies=3) == _lib.LV_ERR_ARG

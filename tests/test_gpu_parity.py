@@ -339,3 +339,36 @@ def test_full_size_single_call_60x30(lv, ctx, orc):
         e = np.abs(gb - r["sum_grad"]).max()
         say(f"  FP64 block {b}: max err / max|partial| {e / scale:.3g}")
         assert e <= F64_GRAD * scale, f"FP64 block {b}"
+
+
+@pytest.mark.parametrize("adjoint", ["stored", "checkpoint"])
+def test_every_tuning_candidate_passes(lv, ctx, orc, adjoint):
+    """The autotuner may pick any of its candidates: each must meet the parity bar."""
+    wl = W.small_call()
+    ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps)
+    cands = lv.tuning_candidates(wl.surface, wl.book.strike, wl.book.maturity, wl.n_paths,
+                                 wl.n_steps, adjoint=adjoint)
+    say(f"  {len(cands)} candidates ({adjoint})")
+    for block, K, win, bpc in cands:
+        opts = dict(block=block, copies=K, blocks_per_cu=bpc, adjoint=adjoint)
+        if adjoint == "stored":
+            opts["window"] = win
+        got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, **opts)
+        assert_parity(got, ref, 32, f"candidate {opts}")
+
+
+def test_autotune_picks_a_candidate(lv, ctx, orc):
+    wl = W.small_call()
+    ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps)
+    got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, autotune=True)
+    info = ctx.run_info()
+    assert info["autotuned"] == 1
+    assert_parity(got, ref, 32, "autotuned")
+    shape = (info["block"], info["copies"], info["window"], info["blocks_per_cu"])
+    assert shape in lv.tuning_candidates(wl.surface, wl.book.strike, wl.book.maturity, wl.n_paths,
+                                         wl.n_steps)
+    # the second call reuses the tuned shape
+    got2 = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, autotune=True)
+    info2 = ctx.run_info()
+    assert (info2["block"], info2["copies"], info2["window"], info2["blocks_per_cu"]) == shape
+    assert np.array_equal(got2["grad"], got["grad"])
