@@ -227,10 +227,17 @@ enum { LV_K_FWD = 0, LV_K_REV = 1, LV_K_FUSED = 2, LV_K_MERGE = 3, LV_K_ZERO = 4
  * clears the totals after reading. */
 lv_status lv_kernel_times(lv_ctx *ctx, double *ms, int64_t *counts, int32_t reset);
 
-/* Test support: copy the per-block gradient partial sums of the last surface of
- * the last pricing call (unnormalised FP64, [n_blocks][I*J], before the merge)
- * to host memory; host_len is the number of doubles host_out holds. */
-lv_status lv_debug_block_grads(lv_ctx *ctx, double *host_out, size_t host_len);
+/* Test support: copy the per-block partial records of the last surface of the last
+ * pricing call to host memory (unnormalised FP64, [n_blocks][2 n_opt + 1 + I*J]:
+ * per option in maturity order sum payoff and sum payoff^2, then sum of
+ * d(value)/d y_0, then the gradient grid), before the merge.  host_len is the
+ * number of doubles host_out holds.  The option order is that of
+ * lv_debug_option_order. */
+lv_status lv_debug_block_partials(lv_ctx *ctx, double *host_out, size_t host_len);
+
+/* Test support: the caller index of each option in the order of the partial
+ * records (options sorted by maturity step, ties in caller order). */
+lv_status lv_debug_option_order(const lv_book *book, int32_t n_steps, int32_t *order_out);
 
 #ifdef __cplusplus
 }

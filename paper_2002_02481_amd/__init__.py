@@ -82,6 +82,14 @@ def make_opts(precision=32, adjoint="stored", ckpt_every=16, use_graph=False, bl
                    int(bool(autotune)))
 
 
+def option_order(maturities, n_steps) -> np.ndarray:
+    """Caller index of each option in the library's maturity order."""
+    book = _Book(np.ones(len(np.atleast_1d(maturities))), maturities)
+    out = np.zeros(book.n, dtype=np.int32)
+    _check_status(_lib_handle().lv_debug_option_order(C.byref(book.c), int(n_steps), out.ctypes.data))
+    return out
+
+
 def tuning_candidates(surface, strikes, maturities, n_paths, n_steps, *, is_put=None,
                       spot_axis=None, time_axis=None, **opts):
     """Launch shapes (block, copies, window, blocks_per_cu) the autotuner would time."""
@@ -136,11 +144,19 @@ class Context:
         _check_status(self.lib.lv_kernel_times(self.h, ms.ctypes.data, cnt.ctypes.data, int(reset)), self.h)
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(_lib.KERNEL_KINDS)}
 
-    def block_grads(self, G: int) -> np.ndarray:
+    def block_partials(self, n_opt: int, G: int) -> dict:
+        """Per-block partial records of the last surface of the last call:
+        sum_pay, sum_pay2 [B, n_opt] (maturity order), sum_lam0 [B], grad [B, G]."""
         B = self.run_info()["n_blocks"]
-        out = np.zeros((B, G))
-        _check_status(self.lib.lv_debug_block_grads(self.h, out.ctypes.data, out.size), self.h)
-        return out
+        Q = 2 * n_opt + 1 + G
+        out = np.zeros((B, Q))
+        _check_status(self.lib.lv_debug_block_partials(self.h, out.ctypes.data, out.size), self.h)
+        pay = out[:, :2 * n_opt].reshape(B, n_opt, 2)
+        return dict(sum_pay=pay[:, :, 0], sum_pay2=pay[:, :, 1], sum_lam0=out[:, 2 * n_opt],
+                    grad=out[:, 2 * n_opt + 1:])
+
+    def block_grads(self, G: int, n_opt: int = 1) -> np.ndarray:
+        return self.block_partials(n_opt, G)["grad"]
 
     def close(self):
         if getattr(self, "h", None):

@@ -82,7 +82,8 @@ SIGNATURES = {
     "lv_debug_philox": (C.c_int, [_vp, _u64, _u64, _i32, _u64, _i64, _vp]),
     "lv_debug_normals": (C.c_int, [_vp, _i32, _u64, _u64, _i64, _i32, _vp]),
     "lv_last_run_info": (C.c_int, [_vp, C.POINTER(lv_run_info)]),
-    "lv_debug_block_grads": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "lv_debug_block_partials": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "lv_debug_option_order": (C.c_int, [_PB, _i32, _vp]),
     "lv_kernel_times": (C.c_int, [_vp, _vp, _vp, _i32]),
     "lv_tuning_candidates": (C.c_int, [_PG, _PB, _i64, _i32, _PO, _vp, _i32, C.POINTER(C.c_int32)]),
 }

@@ -55,11 +55,10 @@ struct lv_ctx {
     int n_cu = 256;
     size_t max_lds = 65536;
     std::string err = "no error";
-    Buf planbuf, part, seg, overflow, states, ckpt, sig_stage, out_stage;
+    Buf planbuf, part, seg, states, ckpt, sig_stage, out_stage;
     std::vector<char> plan_bytes;     // what planbuf holds
     lv_run_info info{};
     int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
-    bool overflow_dirty = false;                 // a call stopped between adjoint and merge
     std::map<std::string, Shape> tuned;          // autotuner results per request shape
     bool last_autotuned = false;
     // kernel timing (lv_opts.profile)
@@ -432,14 +431,6 @@ lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
     lv_status st;
     if ((st = ensure(ctx, ctx->part, (size_t)pl.blocks * pl.Q * 8)) != LV_OK) return st;
     if ((st = ensure(ctx, ctx->seg, (size_t)pl.S * pl.Q * 8)) != LV_OK) return st;
-    const size_t had = ctx->overflow.n;
-    if ((st = ensure(ctx, ctx->overflow, (size_t)pl.G * 8)) != LV_OK) return st;
-    if (ctx->overflow.n != had || ctx->overflow_dirty) {
-        // the merge clears what it reads, so the side grid only needs zeroing when new
-        hipError_t e = lvk::launch_zero((double *)ctx->overflow.p, ctx->overflow.n / 8, ctx->stream());
-        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "zero fill: %s", hipGetErrorString(e));
-        ctx->overflow_dirty = false;
-    }
     if (adjoint && pl.adjoint == LV_ADJ_STORED) {
         const size_t b = (size_t)pl.N * (size_t)pl.P * real_bytes(pl.precision);
         if ((st = ensure(ctx, ctx->states, b)) != LV_OK) return st;
@@ -501,7 +492,6 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
     hipStream_t st = ctx->stream();
     lvk::Args a = make_args(pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
-    a.overflow = (double *)ctx->overflow.p;
     a.states = ctx->states.p;
     a.ckpt = ctx->ckpt.p;
     const bool prof = pl.profile && !capturing;
@@ -510,12 +500,11 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
         e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, false, pl.blocks, pl.block, st); });
         if (e != hipSuccess) return e;
         return timed(ctx, prof, LV_K_MERGE, [&] {
-            return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow,
+            return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S,
                                      pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, nullptr,
                                      nullptr, st);
         });
     }
-    ctx->overflow_dirty = true;
     if (pl.adjoint == LV_ADJ_STORED) {
         e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st); });
         if (e != hipSuccess) return e;
@@ -526,10 +515,9 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
         if (e != hipSuccess) return e;
     }
     e = timed(ctx, prof, LV_K_MERGE, [&] {
-        return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
+        return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                                  pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, grad, delta, st);
     });
-    if (e == hipSuccess && grad) ctx->overflow_dirty = false;
     return e;
 }
 
@@ -662,8 +650,8 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
         return LV_OK;
     }
     const void *ptrs[] = {sigmas_dev, prices, stderrs, grads, deltas, ctx->planbuf.p, ctx->part.p,
-                          ctx->seg.p, ctx->overflow.p, ctx->states.p, ctx->ckpt.p};
-    std::string key = graph_key(pl, ptrs, 11, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
+                          ctx->seg.p, ctx->states.p, ctx->ckpt.p};
+    std::string key = graph_key(pl, ptrs, 10, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
     bool replay = ctx->graph_exec && key == ctx->graph_key;
     if (!replay) {
         if (ctx->graph_exec) {
@@ -739,7 +727,7 @@ void lv_destroy(lv_ctx *ctx) {
         ctx->event_pool.push_back(t.b);
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-    Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->seg, &ctx->overflow, &ctx->states, &ctx->ckpt,
+    Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->seg, &ctx->states, &ctx->ckpt,
                    &ctx->sig_stage, &ctx->out_stage};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -856,11 +844,10 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
     hipStream_t st = ctx->stream();
     lvk::Args a = make_args(pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
-    a.overflow = (double *)ctx->overflow.p;
     a.states = states_dev;
     hipError_t e = lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st);
     if (e == hipSuccess)
-        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
+        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                               pl.G, t.opt_orig, pl.P, pl.spot, price_dev, std_err_dev, nullptr, nullptr, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     record_info(ctx, pl, false, false);
@@ -889,19 +876,16 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     hipStream_t st = ctx->stream();
     lvk::Args a = make_args(pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
-    a.overflow = (double *)ctx->overflow.p;
     a.states = const_cast<void *>(states_dev);
     a.cot = cotangent_dev;
     // the reverse writes no payoff sums: the merge's price outputs go to scratch
-    ctx->overflow_dirty = true;
     hipError_t e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
     double *scratch = (double *)ctx->out_stage.p;
     if (e == hipSuccess)
-        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, a.overflow, pl.n_opt,
+        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                               pl.G, t.opt_orig, pl.P, pl.spot, scratch, scratch + pl.n_opt, grad_dev,
                               delta_dev, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
-    ctx->overflow_dirty = false;
     record_info(ctx, pl, true, false);
     ctx->info.fixed_point_bits = -1000;   // depends on the device cotangent
     return LV_OK;
@@ -976,18 +960,28 @@ lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info) {
     return LV_OK;
 }
 
-lv_status lv_debug_block_grads(lv_ctx *ctx, double *host_out, size_t host_len) {
+lv_status lv_debug_block_partials(lv_ctx *ctx, double *host_out, size_t host_len) {
     if (!ctx || !host_out) return fail(ctx, LV_ERR_ARG, "ctx and host_out are required");
-    const int B = ctx->info.n_blocks, Q = ctx->last_Q, G = ctx->last_G, n_opt = ctx->last_nopt;
-    if (B <= 0 || !ctx->part.p || ctx->info.adjoint == LV_ADJ_NONE)
-        return fail(ctx, LV_ERR_ARG, "no gradient call has run on this context");
-    if (host_len < (size_t)B * G) return fail(ctx, LV_ERR_ARG, "host_out holds %zu doubles, need %zu", host_len, (size_t)B * G);
+    const int B = ctx->info.n_blocks, Q = ctx->last_Q;
+    if (B <= 0 || !ctx->part.p) return fail(ctx, LV_ERR_ARG, "no pricing call has run on this context");
+    if (host_len < (size_t)B * Q) return fail(ctx, LV_ERR_ARG, "host_out holds %zu doubles, need %zu", host_len, (size_t)B * Q);
     HIPCHECK(ctx, hipSetDevice(ctx->device));
-    std::vector<double> h((size_t)B * Q);
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
-    HIPCHECK(ctx, hipMemcpy(h.data(), ctx->part.p, h.size() * 8, hipMemcpyDeviceToHost));
-    for (int b = 0; b < B; ++b)
-        std::memcpy(host_out + (size_t)b * G, h.data() + (size_t)b * Q + 2 * n_opt + 1, (size_t)G * 8);
+    HIPCHECK(ctx, hipMemcpy(host_out, ctx->part.p, (size_t)B * Q * 8, hipMemcpyDeviceToHost));
+    return LV_OK;
+}
+
+lv_status lv_debug_option_order(const lv_book *book, int32_t n_steps, int32_t *order_out) {
+    if (!book || !order_out || book->n_opt < 1 || !book->maturity || n_steps < 1)
+        return fail(nullptr, LV_ERR_ARG, "book, order_out and n_steps >= 1 are required");
+    double tmax = 0.0;
+    for (int k = 0; k < book->n_opt; ++k) tmax = std::max(tmax, book->maturity[k]);
+    std::vector<long long> steps(book->n_opt);
+    for (int k = 0; k < book->n_opt; ++k) steps[k] = std::llround(book->maturity[k] / (tmax / n_steps));
+    std::vector<int> order(book->n_opt);
+    for (int k = 0; k < book->n_opt; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return steps[x] < steps[y]; });
+    for (int k = 0; k < book->n_opt; ++k) order_out[k] = order[k];
     return LV_OK;
 }
 

@@ -36,7 +36,6 @@ struct Args {
     // per-block partial records: [n_blocks][Q], Q = 2 n_opt + 1 + I J
     double *part;
     int Q;
-    double *overflow;           // [I J] rare large adjoint terms (FP64 global atomics)
     // tiling
     int n_tiles;                // path tiles of blockDim paths
     int W;                      // steps per LDS window (multiple of 4)
@@ -56,8 +55,8 @@ hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int 
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_zero(double *p, size_t n, hipStream_t st);
-// Fixed-order merge of part [B][Q] into final outputs; reads and clears overflow.
-hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, double *overflow,
+// Fixed-order merge of part [B][Q] into final outputs.
+hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S,
                         int n_opt, int G, const int *opt_orig, long long P, double spot,
                         double *price, double *stderr_, double *grad, double *delta,
                         hipStream_t st);

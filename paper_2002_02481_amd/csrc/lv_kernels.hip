@@ -20,7 +20,8 @@
 // to spread same-cell collisions.  At each window boundary the owner thread of
 // spot node i folds H into a per-block FP64 grid with the time weights; blocks
 // write their grids once and a fixed-order compensated merge combines them.
-// Terms too large for the fixed-point range take an FP64 global-atomic side path.
+// Terms too large for the fixed-point range take an FP64 LDS-atomic side path into
+// the block's grid.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -309,8 +310,8 @@ __device__ void fold2(const Args &a, const double *Fb, double *g64, int w0, int 
 // Scatter of one step's adjoint term x = gb * 2^F: x(1-f) to node i and x f to
 // node i+1 of window row wn, in this lane's copy column Hl (= H + lane copy).
 template <typename R>
-__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl, int wn, int n,
-                                        const Look<R> &L, R gb, R sc, R qm) {
+__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl, double *g64, int wn,
+                                        int n, const Look<R> &L, R gb, R sc, R qm) {
     typedef typename Math<R>::Acc Acc;
     const R x = gb * sc;
     if (x == (R)0) return;
@@ -321,14 +322,15 @@ __device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl
         Math<R>::acc_add(h, q0);
         Math<R>::acc_add(h + a.K, q1);
     } else {
-        // rare: outside the fixed-point range (or not finite): FP64 global atomics
+        // rare: outside the fixed-point range (or not finite): FP64 LDS atomics
+        // straight into the block's grid (no fold runs while steps scatter)
         const int j = a.tj[n];
         const double al = a.ta[n], g = (double)gb, f = (double)L.f;
         const int J = a.J;
-        atomicAdd(&a.overflow[L.i * J + j], g * (1.0 - f) * (1.0 - al));
-        atomicAdd(&a.overflow[(L.i + 1) * J + j], g * f * (1.0 - al));
-        atomicAdd(&a.overflow[L.i * J + j + 1], g * (1.0 - f) * al);
-        atomicAdd(&a.overflow[(L.i + 1) * J + j + 1], g * f * al);
+        atomicAdd(&g64[L.i * J + j], g * (1.0 - f) * (1.0 - al));
+        atomicAdd(&g64[(L.i + 1) * J + j], g * f * (1.0 - al));
+        atomicAdd(&g64[L.i * J + j + 1], g * (1.0 - f) * al);
+        atomicAdd(&g64[(L.i + 1) * J + j + 1], g * f * al);
     }
 }
 
@@ -503,7 +505,7 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
                         }
                         const R gb = lam * cc[r];
                         lam = fma(lam * cc[r], dsd[r], lam);
-                        scatter<R>(a, Hl, wn0 + r, n, L[r], gb, sc, qm);
+                        scatter<R>(a, Hl, g64, wn0 + r, n, L[r], gb, sc, qm);
                     }
                 }
             };
@@ -675,7 +677,7 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
                         const R c = cs[k];
                         const R gb = lam * c;
                         lam = fma(lam * c, dsd[r], lam);
-                        scatter<R>(a, Hl, k, n, L[r], gb, sc, qm);
+                        scatter<R>(a, Hl, g64, k, n, L[r], gb, sc, qm);
                         y_next = ys[k];
                     }
                 }
@@ -748,9 +750,8 @@ __device__ __forceinline__ double seg_total(const double *seg, int S, int Q, int
     return sum + comp;
 }
 
-// Level 2 and finalisation.  The rare-term FP64 side grid is read and cleared
-// here, so it is zero again for the next call.
-__global__ void k_merge2(const double *seg, int S, int Q, double *overflow, int n_opt, int G,
+// Level 2 and finalisation.
+__global__ void k_merge2(const double *seg, int S, int Q, int n_opt, int G,
                          const int *opt_orig, long long P, double spot, double *price,
                          double *stderr_, double *grad, double *delta) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -765,8 +766,7 @@ __global__ void k_merge2(const double *seg, int S, int Q, double *overflow, int 
         if (delta) *delta = seg_total(seg, S, Q, 2 * n_opt) / Pd / spot;
     } else if (grad && t < n_opt + 1 + G) {
         const int q = t - n_opt - 1;
-        grad[q] = (seg_total(seg, S, Q, 2 * n_opt + 1 + q) + overflow[q]) / Pd;
-        overflow[q] = 0.0;
+        grad[q] = seg_total(seg, S, Q, 2 * n_opt + 1 + q) / Pd;
     }
 }
 
@@ -900,7 +900,7 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, double *overflow,
+hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S,
                         int n_opt, int G, const int *opt_orig, long long P, double spot,
                         double *price, double *stderr_, double *grad, double *delta,
                         hipStream_t st) {
@@ -910,7 +910,7 @@ hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S, do
     if (e != hipSuccess) return e;
     // k_merge2 reads seg with row stride Q; k_merge1 wrote rows of stride Q.
     const int T = n_opt + 1 + (grad ? G : 0);
-    hipLaunchKernelGGL(k_merge2, dim3((T + 255) / 256), dim3(256), 0, st, seg, S, Q, overflow, n_opt,
+    hipLaunchKernelGGL(k_merge2, dim3((T + 255) / 256), dim3(256), 0, st, seg, S, Q, n_opt,
                        G, opt_orig, P, spot, price, stderr_, grad, delta);
     return hipGetLastError();
 }

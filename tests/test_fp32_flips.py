@@ -1,0 +1,57 @@
+"""Why the FP32 gradient bar is stated in standard errors (CPU, oracle only).
+
+The pathwise derivative of a bilinearly interpolated surface jumps at spot nodes.
+Rounding the oracle's FP64 state to float32 after every step -- and changing
+nothing else -- already moves single gradient buckets by far more than 1e-4 max|g|
+on the long-horizon noisy surface, while staying within a fraction of the Monte
+Carlo standard error; on the short smile surface the effect is negligible.  The
+float32-state variant is planted in a copy of the oracle source, never in the
+oracle itself.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+STATE_UPDATE = "w->y[n + 1] = w->y[n] - 0.5 * s * s * dt + s * sdt * w->z[n];"
+
+
+@pytest.fixture(scope="module")
+def f32_state_oracle(tmp_path_factory):
+    d = tmp_path_factory.mktemp("f32state")
+    src = open(oracle.SOURCE).read()
+    assert src.count(STATE_UPDATE) == 1
+    path = d / "f32state.c"
+    path.write_text(src.replace(STATE_UPDATE, "w->y[n + 1] = (double)(float)(w->y[n] - 0.5 * s * s * dt + s * sdt * w->z[n]);"))
+    return oracle.Oracle(oracle.build(str(path), str(d / "libf32state.so")))
+
+
+def _compare(o64, o32, surface, book, n_steps, P, n_batches=16):
+    a = o64.price_and_grad(surface, book, P, n_steps)
+    b = o32.price_and_grad(surface, book, P, n_steps)
+    per = P // n_batches
+    gs = np.array([o64.sums(surface, book, n_steps, 0, [(k * per, (k + 1) * per)])["sum_grad"] / per
+                   for k in range(n_batches)])
+    se = gs.std(axis=0, ddof=1) / np.sqrt(n_batches)
+    err = np.abs(a["grad"] - b["grad"])
+    return a, b, err, se
+
+
+def test_long_horizon_flips(f32_state_oracle):
+    o64 = oracle.default()
+    s = W.wide_surface(1).rounded_to_f32()
+    a, b, err, se = _compare(o64, f32_state_oracle, s, W.call(100.0, 5.0), 260, 1 << 16)
+    gmax = np.abs(a["grad"]).max()
+    assert abs(a["price"][0] - b["price"][0]) < 1e-5 * 100        # prices are unaffected
+    assert err.max() > 1e-4 * gmax                                # buckets are not
+    big = err > 1e-4 * gmax
+    assert np.all(err[big] <= 2.5 * se[big])                      # but stay within the MC error
+
+
+def test_short_horizon_negligible(f32_state_oracle):
+    o64 = oracle.default()
+    wl = W.small_call()
+    s = wl.surface.rounded_to_f32()
+    a, b, err, se = _compare(o64, f32_state_oracle, s, wl.book, wl.n_steps, wl.n_paths)
+    assert err.max() <= 1e-5 * np.abs(a["grad"]).max()
