@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64/forward/checkpoint variants")
-    ap.add_argument("--launch", default="", metavar="BLOCK,COPIES,WINDOW,BPC",
+    ap.add_argument("--launch", default="", metavar="BLOCK,COPIES,WINDOW,BPC,FWD_BLOCK,FWD_BPC",
                     help="fix the launch shape instead of autotuning it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
@@ -101,14 +101,16 @@ def main():
         return lv.price_and_grad_dev(sig, 100.0, strikes, mats, P, N, wl.seed, out=out, **kw, **opts)
 
     if args.launch:
-        bl, k, w, c = (int(x) for x in args.launch.split(","))
-        out = [t for t in base_run(block=bl, copies=k, window=w, blocks_per_cu=c)]
+        bl, k, w, c, fb, fc = (int(x) for x in args.launch.split(","))
+        out = [t for t in base_run(block=bl, copies=k, window=w, blocks_per_cu=c, fwd_block=fb,
+                                   fwd_blocks_per_cu=fc)]
     else:
         out = [t for t in base_run(autotune=True)]      # first call tunes the launch shape
     torch.cuda.synchronize()
     info = ctx.run_info()
     shape = dict(block=info["block"], copies=info["copies"], window=info["window"],
-                 blocks_per_cu=info["blocks_per_cu"])
+                 blocks_per_cu=info["blocks_per_cu"], fwd_block=info["fwd_block"],
+                 fwd_blocks_per_cu=info["fwd_blocks_per_cu"])
 
     def run(out=None, **opts):
         for k, v in shape.items():

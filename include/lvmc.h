@@ -107,7 +107,10 @@ typedef struct {
                                with lv_kernel_times */
     int32_t autotune;       /* 1: on the first call of a shape (grid, steps, paths, book size,
                                precision, adjoint), time every candidate launch shape that the
-                               fields above leave free and keep the fastest for this context */
+                               shape fields leave free and keep the fastest for this context */
+    int32_t fwd_block;      /* threads per block of the separate forward kernel (stored and
+                               price-only paths); 0 = tuned default */
+    int32_t fwd_blocks_per_cu; /* persistent blocks per CU of that forward kernel; 0 = default */
 } lv_opts;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`
@@ -205,13 +208,19 @@ typedef struct {
     int32_t window;             /* steps per LDS window (the segment for the checkpoint kernel) */
     int32_t blocks_per_cu;      /* persistent blocks per CU asked for */
     int32_t autotuned;          /* 1 if the shape came from the autotuner */
+    int32_t fwd_block;          /* threads per block of the separate forward kernel */
+    int32_t fwd_blocks_per_cu;  /* its blocks per CU asked for */
+    int32_t fwd_blocks;         /* its grid (its payoff partials are records 0 .. fwd_blocks-1) */
     int64_t overflow_terms;     /* reserved: 0 */
 } lv_run_info;
 
 /* The launch shapes the autotuner would time for this request, as rows of
- * (block, copies, window, blocks_per_cu) in shapes_out (host int32 [max][4]);
- * *n_out receives the number of rows written.  Host only (device 0's
- * properties are read when a device is present, else 256 CUs are assumed). */
+ * (block, copies, window, blocks_per_cu, fwd_block, fwd_blocks_per_cu) in
+ * shapes_out (host int32 [max][6]): the adjoint-kernel candidates with the
+ * default forward shape, then the forward candidates with the default adjoint
+ * shape (the two kernels are tuned one after the other).  *n_out receives the
+ * number of rows written.  Host only (device 0's properties are read when a
+ * device is present, else 256 CUs are assumed). */
 lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t n_paths,
                                int32_t n_steps, const lv_opts *opts, int32_t *shapes_out,
                                int32_t max, int32_t *n_out);

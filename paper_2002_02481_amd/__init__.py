@@ -75,11 +75,12 @@ class _Book:
 
 
 def make_opts(precision=32, adjoint="stored", ckpt_every=16, use_graph=False, block=0,
-              blocks_per_cu=0, copies=0, window=0, profile=False, autotune=False) -> lv_opts:
+              blocks_per_cu=0, copies=0, window=0, profile=False, autotune=False, fwd_block=0,
+              fwd_blocks_per_cu=0) -> lv_opts:
     adj = ADJOINT[adjoint] if isinstance(adjoint, str) else int(adjoint)
     return lv_opts(int(precision), adj, int(ckpt_every), int(bool(use_graph)), int(block),
                    int(blocks_per_cu), int(copies), int(window), int(bool(profile)),
-                   int(bool(autotune)))
+                   int(bool(autotune)), int(fwd_block), int(fwd_blocks_per_cu))
 
 
 def option_order(maturities, n_steps) -> np.ndarray:
@@ -92,11 +93,12 @@ def option_order(maturities, n_steps) -> np.ndarray:
 
 def tuning_candidates(surface, strikes, maturities, n_paths, n_steps, *, is_put=None,
                       spot_axis=None, time_axis=None, **opts):
-    """Launch shapes (block, copies, window, blocks_per_cu) the autotuner would time."""
+    """Launch shapes (block, copies, window, blocks_per_cu, fwd_block, fwd_blocks_per_cu)
+    the autotuner would time."""
     grid, _ = _surface_parts(surface, spot_axis, time_axis)
     book = _Book(strikes, maturities, is_put, None)
     o = make_opts(**opts)
-    out = np.zeros((512, 4), dtype=np.int32)
+    out = np.zeros((512, 6), dtype=np.int32)
     n = C.c_int32()
     _check_status(_lib_handle().lv_tuning_candidates(C.byref(grid), C.byref(book.c), int(n_paths),
                                                      int(n_steps), C.byref(o), out.ctypes.data,

@@ -26,7 +26,8 @@ struct Buf {
 
 // Launch shape: threads per block, histogram copies, window (steps), blocks per CU.
 struct Shape {
-    int block = 512, K = 2, W = 16, bpc = 2;
+    int block = 512, K = 2, W = 16, bpc = 2;   // adjoint (or fused) kernel
+    int fblock = 512, fbpc = 2;                // separate forward kernel
 };
 
 // Everything derived from one request: the time table, the book in maturity
@@ -41,8 +42,9 @@ struct Plan {
     std::vector<double> ta, opt_strike, weight;
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;
     int block = 256, blocks = 0, n_tiles = 0, W = 16, K = 8, S = 32, bpc = 2;
+    int fblock = 256, fblocks = 0, f_n_tiles = 0, fbpc = 2;
     int G = 0, Q = 0;
-    Shape user;            // caller-fixed shape fields (0 = free)
+    Shape user{0, 0, 0, 0, 0, 0};   // caller-fixed shape fields (0 = free)
     bool autotune = false;
 };
 
@@ -133,7 +135,7 @@ size_t lds_need(const Plan &pl, const Shape &sh) {
     const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
     const int W = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W;
     size_t a = lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, W, sh.K);
-    size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, W, sh.K);
+    size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, sh.fblock, W, sh.K);
     return std::max(a, b);
 }
 
@@ -146,6 +148,8 @@ Shape default_shape(const Plan &pl, int n_cu) {
     sh.K = 2;
     sh.W = 32;
     sh.bpc = 2;
+    sh.fblock = (int)std::min<long long>(512, std::max<long long>(64, floor_pow2(pl.P / (2 * n_cu))));
+    sh.fbpc = 4;
     return sh;
 }
 
@@ -167,31 +171,56 @@ lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds,
     pl.bpc = sh.bpc;
     pl.n_tiles = (int)((pl.P + pl.block - 1) / pl.block);
     pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * sh.bpc);
-    pl.S = std::min(64, pl.blocks);
+    pl.fblock = sh.fblock;
+    pl.fbpc = sh.fbpc;
+    pl.f_n_tiles = (int)((pl.P + pl.fblock - 1) / pl.fblock);
+    pl.fblocks = (int)std::min<long long>(pl.f_n_tiles, (long long)n_cu * sh.fbpc);
+    // two merge levels of about sqrt(records) loads each
+    const int recs = std::max(pl.blocks, pl.fblocks);
+    pl.S = std::max(1, std::min(recs, (int)std::lround(std::sqrt((double)recs))));
     return LV_OK;
 }
 
-// Candidate shapes the autotuner times (every one is a valid launch).
-std::vector<Shape> tuning_candidates(const Plan &pl, int n_cu, size_t max_lds) {
+// Candidate shapes the autotuner times (every one is a valid launch): first the
+// forward kernel's (block, blocks per CU) with the default adjoint shape, then the
+// adjoint kernel's (block, copies, window, blocks per CU) with the chosen forward.
+std::vector<Shape> forward_candidates(const Plan &pl, const Shape &base, int n_cu, size_t max_lds) {
+    std::vector<Shape> out;
+    if (pl.adjoint == LV_ADJ_CHECKPOINT) return out;   // the fused kernel has no separate forward
+    const int bmax = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(2 * pl.P / n_cu)));
+    for (int b : {128, 256, 512, 1024}) {
+        if (b > bmax && b != 128) continue;
+        for (int c : {1, 2, 4, 8}) {
+            Shape sh = base;
+            sh.fblock = b;
+            sh.fbpc = c;
+            if (lds_need(pl, sh) > std::min<size_t>(max_lds, 65536)) continue;
+            out.push_back(sh);
+        }
+    }
+    return out;
+}
+
+std::vector<Shape> adjoint_candidates(const Plan &pl, const Shape &base, int n_cu, size_t max_lds) {
     std::vector<Shape> out;
     const int bmax = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(2 * pl.P / n_cu)));
-    const int blocks[] = {128, 256, 512, 1024};
-    const int ks[] = {1, 2, 4};
-    const int ws[] = {8, 16, 32};
-    const int bpcs[] = {1, 2, 4};
-    for (int b : blocks) {
+    for (int b : {128, 256, 512, 1024}) {
         if (b > bmax && b != 128) continue;
-        for (int k : ks)
-            for (int w : ws) {
+        for (int k : {1, 2, 4})
+            for (int w : {8, 16, 32}) {
                 if (pl.adjoint == LV_ADJ_CHECKPOINT && w != 8) continue;   // window = segment
-                for (int c : bpcs) {
-                    Shape sh{b, k, w, c};
+                for (int c : {1, 2, 4}) {
+                    Shape sh = base;
+                    sh.block = b;
+                    sh.K = k;
+                    sh.W = w;
+                    sh.bpc = c;
                     if (lds_need(pl, sh) > std::min<size_t>(max_lds, 65536)) continue;
                     out.push_back(sh);
                 }
             }
     }
-    if (out.empty()) out.push_back(default_shape(pl, n_cu));
+    if (out.empty()) out.push_back(base);
     return out;
 }
 
@@ -322,7 +351,13 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     pl.user.K = o.copies;
     pl.user.W = o.window;
     pl.user.bpc = o.blocks_per_cu;
+    pl.user.fblock = o.fwd_block;
+    pl.user.fbpc = o.fwd_blocks_per_cu;
     pl.autotune = o.autotune != 0;
+    if (o.fwd_block != 0 && (o.fwd_block % 64 != 0 || o.fwd_block < 64 || o.fwd_block > 1024))
+        return fail(ctx, LV_ERR_ARG, "fwd_block must be a multiple of 64 in [64, 1024]");
+    if (o.fwd_blocks_per_cu < 0 || o.fwd_blocks_per_cu > 64)
+        return fail(ctx, LV_ERR_ARG, "fwd_blocks_per_cu must be in [0, 64]");
     if (o.copies && (o.copies & (o.copies - 1)))
         return fail(ctx, LV_ERR_ARG, "copies must be a power of two");
     Shape sh = default_shape(pl, n_cu);
@@ -330,6 +365,8 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     if (o.copies) sh.K = o.copies;
     if (o.window) sh.W = o.window;
     if (o.blocks_per_cu) sh.bpc = o.blocks_per_cu;
+    if (o.fwd_block) sh.fblock = o.fwd_block;
+    if (o.fwd_blocks_per_cu) sh.fbpc = o.fwd_blocks_per_cu;
     return apply_shape(ctx, pl, sh, n_cu, max_lds, !o.copies, !o.window);
 }
 
@@ -429,7 +466,7 @@ size_t real_bytes(int precision) { return precision == 64 ? 8 : 4; }
 // Workspace for the fused paths.
 lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
     lv_status st;
-    if ((st = ensure(ctx, ctx->part, (size_t)pl.blocks * pl.Q * 8)) != LV_OK) return st;
+    if ((st = ensure(ctx, ctx->part, (size_t)std::max(pl.blocks, pl.fblocks) * pl.Q * 8)) != LV_OK) return st;
     if ((st = ensure(ctx, ctx->seg, (size_t)pl.S * pl.Q * 8)) != LV_OK) return st;
     if (adjoint && pl.adjoint == LV_ADJ_STORED) {
         const size_t b = (size_t)pl.N * (size_t)pl.P * real_bytes(pl.precision);
@@ -496,26 +533,30 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
     a.ckpt = ctx->ckpt.p;
     const bool prof = pl.profile && !capturing;
     hipError_t e;
+    lvk::Args af = a;                 // the forward kernel's own tiling
+    af.n_tiles = pl.f_n_tiles;
     if (!adjoint) {
-        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, false, pl.blocks, pl.block, st); });
+        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(af, pl.precision, false, pl.fblocks, pl.fblock, st); });
         if (e != hipSuccess) return e;
         return timed(ctx, prof, LV_K_MERGE, [&] {
-            return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S,
+            return lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S,
                                      pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, nullptr,
                                      nullptr, st);
         });
     }
+    int b_pay = pl.blocks;
     if (pl.adjoint == LV_ADJ_STORED) {
-        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st); });
+        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(af, pl.precision, true, pl.fblocks, pl.fblock, st); });
         if (e != hipSuccess) return e;
         e = timed(ctx, prof, LV_K_REV, [&] { return lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st); });
         if (e != hipSuccess) return e;
+        b_pay = pl.fblocks;
     } else {
         e = timed(ctx, prof, LV_K_FUSED, [&] { return lvk::launch_fused_ckpt(a, pl.precision, pl.blocks, pl.block, st); });
         if (e != hipSuccess) return e;
     }
     e = timed(ctx, prof, LV_K_MERGE, [&] {
-        return lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
+        return lvk::launch_merge(a.part, b_pay, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                                  pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, grad, delta, st);
     });
     return e;
@@ -537,15 +578,18 @@ void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
     ctx->info.window = pl.W;
     ctx->info.blocks_per_cu = pl.bpc;
     ctx->info.autotuned = ctx->last_autotuned ? 1 : 0;
+    ctx->info.fwd_block = pl.fblock;
+    ctx->info.fwd_blocks_per_cu = pl.fbpc;
+    ctx->info.fwd_blocks = pl.fblocks;
     ctx->info.overflow_terms = 0;
 }
 
 std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf, bool adjoint) {
     std::string k;
     char buf[128];
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I, pl.J, pl.N,
-             pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
-             pl.blocks, pl.W, pl.K, pl.spot, pl.dt, n_surf);
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I, pl.J,
+             pl.N, pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
+             pl.blocks, pl.W, pl.K, pl.fblock, pl.fblocks, pl.spot, pl.dt, n_surf);
     k += buf;
     k += adjoint ? "A|" : "F|";
     for (int i = 0; i < n_ptrs; ++i) {
@@ -557,9 +601,10 @@ std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf
 
 std::string tune_key(const Plan &pl, bool adjoint) {
     char buf[256];
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N, pl.axis,
-             pl.P, pl.precision, adjoint ? pl.adjoint : LV_ADJ_NONE, pl.seg, pl.n_opt, pl.n_taps,
-             pl.user.block, pl.user.K, pl.user.W, pl.user.bpc, (int)pl.profile);
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N,
+             pl.axis, pl.P, pl.precision, adjoint ? pl.adjoint : LV_ADJ_NONE, pl.seg, pl.n_opt,
+             pl.n_taps, pl.user.block, pl.user.K, pl.user.W, pl.user.bpc, pl.user.fblock,
+             pl.user.fbpc, (int)pl.profile);
     return buf;
 }
 
@@ -567,49 +612,64 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
                   bool adjoint, bool use_graph, double *prices, double *stderrs, double *grads,
                   double *deltas);
 
-// Time every candidate shape the caller left free on the first surface and keep
-// the fastest (per context and request shape).
+// Time one launch shape on the first surface: one untimed run (allocations,
+// first touch), then two timed runs.
+lv_status time_shape(lv_ctx *ctx, const Plan &pl, const Shape &c, const double *sigmas_dev, bool adjoint,
+                     double *prices, double *stderrs, double *grads, double *deltas, hipEvent_t e0,
+                     hipEvent_t e1, float *ms) {
+    Plan q = pl;
+    q.autotune = false;
+    q.profile = 0;
+    lv_status st = apply_shape(ctx, q, c, ctx->n_cu, ctx->max_lds, false, false);
+    if (st != LV_OK) return st;
+    if ((st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas)) != LV_OK) return st;
+    hipError_t e = hipEventRecord(e0, ctx->stream());
+    for (int r = 0; r < 2 && st == LV_OK; ++r)
+        st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas);
+    if (st != LV_OK) return st;
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream());
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+    return LV_OK;
+}
+
+bool user_allows(const Plan &pl, const Shape &c) {
+    return !((pl.user.block && c.block != pl.user.block) || (pl.user.K && c.K != pl.user.K) ||
+             (pl.user.W && c.W != pl.user.W) || (pl.user.bpc && c.bpc != pl.user.bpc) ||
+             (pl.user.fblock && c.fblock != pl.user.fblock) || (pl.user.fbpc && c.fbpc != pl.user.fbpc));
+}
+
+// Autotuner: the separate forward kernel's shape first (stored and price-only
+// paths), then the adjoint (or fused) kernel's shape with that forward; each
+// candidate is timed on the first surface and the fastest kept per context and
+// request shape.
 lv_status autotune(lv_ctx *ctx, Plan &pl, const double *sigmas_dev, bool adjoint, double *prices,
                    double *stderrs, double *grads, double *deltas) {
     const std::string key = tune_key(pl, adjoint);
     auto it = ctx->tuned.find(key);
     if (it == ctx->tuned.end()) {
-        std::vector<Shape> cands;
-        for (const Shape &c : tuning_candidates(pl, ctx->n_cu, ctx->max_lds)) {
-            if ((pl.user.block && c.block != pl.user.block) || (pl.user.K && c.K != pl.user.K) ||
-                (pl.user.W && c.W != pl.user.W) || (pl.user.bpc && c.bpc != pl.user.bpc))
-                continue;
-            cands.push_back(c);
-        }
-        if (cands.empty()) cands.push_back(Shape{pl.block, pl.K, pl.W, pl.bpc});
+        Shape best{pl.block, pl.K, pl.W, pl.bpc, pl.fblock, pl.fbpc};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         HIPCHECK(ctx, hipEventCreate(&e0));
         HIPCHECK(ctx, hipEventCreate(&e1));
-        Shape best = cands[0];
-        float best_ms = 1e30f;
         lv_status st = LV_OK;
-        for (const Shape &c : cands) {
-            Plan q = pl;
-            q.autotune = false;
-            q.profile = 0;
-            if ((st = apply_shape(ctx, q, c, ctx->n_cu, ctx->max_lds, false, false)) != LV_OK) break;
-            // one untimed run (allocations, first-touch), then two timed runs
-            if ((st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas)) != LV_OK) break;
-            hipError_t e = hipEventRecord(e0, ctx->stream());
-            for (int r = 0; r < 2 && st == LV_OK; ++r)
-                st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas);
-            if (st != LV_OK) break;
-            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream());
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                st = fail(ctx, LV_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
-                break;
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
+        for (int phase = 0; phase < 2 && st == LV_OK; ++phase) {
+            std::vector<Shape> cands;
+            if (phase == 0 && (!adjoint || pl.adjoint == LV_ADJ_STORED))
+                cands = forward_candidates(pl, best, ctx->n_cu, ctx->max_lds);
+            if (phase == 1 && adjoint) cands = adjoint_candidates(pl, best, ctx->n_cu, ctx->max_lds);
+            float best_ms = 1e30f;
+            for (const Shape &c : cands) {
+                if (!user_allows(pl, c)) continue;
+                float ms = 0.f;
+                if ((st = time_shape(ctx, pl, c, sigmas_dev, adjoint, prices, stderrs, grads, deltas, e0, e1,
+                                     &ms)) != LV_OK)
+                    break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
             }
         }
         (void)hipEventDestroy(e0);
@@ -845,9 +905,10 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
     lvk::Args a = make_args(pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
     a.states = states_dev;
-    hipError_t e = lvk::launch_fwd(a, pl.precision, true, pl.blocks, pl.block, st);
+    a.n_tiles = pl.f_n_tiles;
+    hipError_t e = lvk::launch_fwd(a, pl.precision, true, pl.fblocks, pl.fblock, st);
     if (e == hipSuccess)
-        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
+        e = lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                               pl.G, t.opt_orig, pl.P, pl.spot, price_dev, std_err_dev, nullptr, nullptr, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     record_info(ctx, pl, false, false);
@@ -882,7 +943,7 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     hipError_t e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
     double *scratch = (double *)ctx->out_stage.p;
     if (e == hipSuccess)
-        e = lvk::launch_merge(a.part, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
+        e = lvk::launch_merge(a.part, pl.blocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                               pl.G, t.opt_orig, pl.P, pl.spot, scratch, scratch + pl.n_opt, grad_dev,
                               delta_dev, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -942,12 +1003,18 @@ lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t
                                max_lds, pl);
     if (s != LV_OK) return s;
     int n = 0;
-    for (const Shape &c : tuning_candidates(pl, n_cu, max_lds)) {
+    const Shape base{pl.block, pl.K, pl.W, pl.bpc, pl.fblock, pl.fbpc};
+    std::vector<Shape> rows = adjoint_candidates(pl, base, n_cu, max_lds);
+    for (const Shape &c : forward_candidates(pl, base, n_cu, max_lds)) rows.push_back(c);
+    for (const Shape &c : rows) {
         if (n >= max) break;
-        shapes_out[4 * n + 0] = c.block;
-        shapes_out[4 * n + 1] = c.K;
-        shapes_out[4 * n + 2] = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : c.W;
-        shapes_out[4 * n + 3] = c.bpc;
+        int32_t *r = shapes_out + 6 * n;
+        r[0] = c.block;
+        r[1] = c.K;
+        r[2] = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : c.W;
+        r[3] = c.bpc;
+        r[4] = c.fblock;
+        r[5] = c.fbpc;
         ++n;
     }
     *n_out = n;

@@ -55,8 +55,9 @@ hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int 
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_zero(double *p, size_t n, hipStream_t st);
-// Fixed-order merge of part [B][Q] into final outputs.
-hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S,
+// Fixed-order merge of part [records][Q] into final outputs: payoff entries over
+// the first B_pay records, the rest over the first B_grad.
+hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, double *seg, int S,
                         int n_opt, int G, const int *opt_orig, long long P, double spot,
                         double *price, double *stderr_, double *grad, double *delta,
                         hipStream_t st);

@@ -717,23 +717,27 @@ __device__ __forceinline__ void neumaier(double &sum, double &comp, double x) {
     sum = t;
 }
 
-// Level 1: thread (q, s) sums blocks [B s / S, B (s+1) / S) of entry q in block
-// order; loads are issued in batches of 8 before the compensated adds.
-__global__ void k_merge1(const double *part, int B, int Q, int S, double *seg) {
+// Level 1: thread (q, s) sums records [B s / S, B (s+1) / S) of entry q in record
+// order, B = the payoff kernel's grid for the payoff entries (q < n_pay) and the
+// adjoint kernel's grid for the rest; loads are issued in batches of 8 before the
+// compensated adds.
+__global__ void k_merge1(const double *part, int B_pay, int B_grad, int n_pay, int Qr, int Qm, int S,
+                         double *seg) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
-    if (q >= Q) return;
+    if (q >= Qm) return;
+    const int B = q < n_pay ? B_pay : B_grad;
     const int b0 = (int)((long long)B * s / S), b1 = (int)((long long)B * (s + 1) / S);
     double sum = 0.0, comp = 0.0;
     int b = b0;
     for (; b + 8 <= b1; b += 8) {
         double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = part[(size_t)(b + k) * Q + q];
+        for (int k = 0; k < 8; ++k) v[k] = part[(size_t)(b + k) * Qr + q];
 #pragma unroll
         for (int k = 0; k < 8; ++k) neumaier(sum, comp, v[k]);
     }
-    for (; b < b1; ++b) neumaier(sum, comp, part[(size_t)b * Q + q]);
-    seg[(size_t)s * Q + q] = sum + comp;
+    for (; b < b1; ++b) neumaier(sum, comp, part[(size_t)b * Qr + q]);
+    seg[(size_t)s * Qm + q] = sum + comp;
 }
 
 __device__ __forceinline__ double seg_total(const double *seg, int S, int Q, int q) {
@@ -900,17 +904,18 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const double *part, int B, int Q, double *seg, int S,
+hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, double *seg, int S,
                         int n_opt, int G, const int *opt_orig, long long P, double spot,
                         double *price, double *stderr_, double *grad, double *delta,
                         hipStream_t st) {
-    const int Qm = grad ? Q : 2 * n_opt + 1;   // entries merged
-    hipLaunchKernelGGL(k_merge1, dim3((Qm + 255) / 256, S), dim3(256), 0, st, part, B, Q, S, seg);
+    const int Qm = (grad || delta) ? Q : 2 * n_opt;   // entries merged
+    hipLaunchKernelGGL(k_merge1, dim3((Qm + 255) / 256, S), dim3(256), 0, st, part, B_pay, B_grad,
+                       2 * n_opt, Q, Qm, S, seg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // k_merge2 reads seg with row stride Q; k_merge1 wrote rows of stride Q.
+    // k_merge1 wrote rows of stride Qm; k_merge2 reads them with that stride.
     const int T = n_opt + 1 + (grad ? G : 0);
-    hipLaunchKernelGGL(k_merge2, dim3((T + 255) / 256), dim3(256), 0, st, seg, S, Q, n_opt,
+    hipLaunchKernelGGL(k_merge2, dim3((T + 255) / 256), dim3(256), 0, st, seg, S, Qm, n_opt,
                        G, opt_orig, P, spot, price, stderr_, grad, delta);
     return hipGetLastError();
 }

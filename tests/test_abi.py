@@ -96,15 +96,16 @@ def test_tuning_candidates_are_valid_shapes():
     for adjoint in ("stored", "checkpoint"):
         c = lv.tuning_candidates(s, [100.0], [3.0], 524288, 156, adjoint=adjoint)
         assert len(c) >= 4
-        for block, K, win, bpc in c:
-            assert block % 64 == 0 and 64 <= block <= 1024
-            assert K in (1, 2, 4) and bpc in (1, 2, 4)
+        for block, K, win, bpc, fblock, fbpc in c:
+            assert block % 64 == 0 and 64 <= block <= 1024 and fblock % 64 == 0 and fblock <= 1024
+            assert K in (1, 2, 4) and bpc in (1, 2, 4) and fbpc in (1, 2, 4, 8)
             assert win % 4 == 0
         if adjoint == "checkpoint":
-            assert all(w == 16 for _, _, w, _ in c)
-    # fixed fields of the request restrict nothing here: the candidate grid is the tuner's
+            assert all(r[2] == 16 for r in c)
+        else:
+            assert len({(r[4], r[5]) for r in c}) > 1      # forward shapes are tuned too
     small = lv.tuning_candidates(W.small_surface(), [100.0], [1.0], 16384, 52)
-    assert all(b <= 128 for b, _, _, _ in small)
+    assert all(r[0] <= 128 and r[4] <= 128 for r in small)
 
 
 def test_copies_must_be_power_of_two():

@@ -349,8 +349,9 @@ def test_every_tuning_candidate_passes(lv, ctx, orc, adjoint):
     cands = lv.tuning_candidates(wl.surface, wl.book.strike, wl.book.maturity, wl.n_paths,
                                  wl.n_steps, adjoint=adjoint)
     say(f"  {len(cands)} candidates ({adjoint})")
-    for block, K, win, bpc in cands:
-        opts = dict(block=block, copies=K, blocks_per_cu=bpc, adjoint=adjoint)
+    for block, K, win, bpc, fblock, fbpc in cands:
+        opts = dict(block=block, copies=K, blocks_per_cu=bpc, adjoint=adjoint, fwd_block=fblock,
+                    fwd_blocks_per_cu=fbpc)
         if adjoint == "stored":
             opts["window"] = win
         got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, **opts)
@@ -364,13 +365,14 @@ def test_autotune_picks_a_candidate(lv, ctx, orc):
     info = ctx.run_info()
     assert info["autotuned"] == 1
     assert_parity(got, ref, 32, "autotuned")
-    shape = (info["block"], info["copies"], info["window"], info["blocks_per_cu"])
-    assert shape in lv.tuning_candidates(wl.surface, wl.book.strike, wl.book.maturity, wl.n_paths,
-                                         wl.n_steps)
+    keys = ("block", "copies", "window", "blocks_per_cu", "fwd_block", "fwd_blocks_per_cu")
+    shape = tuple(info[k] for k in keys)
+    rows = lv.tuning_candidates(wl.surface, wl.book.strike, wl.book.maturity, wl.n_paths, wl.n_steps)
+    assert shape[:4] in {r[:4] for r in rows} and shape[4:] in {r[4:] for r in rows}
     # the second call reuses the tuned shape
     got2 = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, autotune=True)
     info2 = ctx.run_info()
-    assert (info2["block"], info2["copies"], info2["window"], info2["blocks_per_cu"]) == shape
+    assert tuple(info2[k] for k in keys) == shape
     assert np.array_equal(got2["grad"], got["grad"])
 
 
