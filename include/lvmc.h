@@ -29,7 +29,10 @@
  * Time grid: dt = max_k maturity_k / n_steps; each maturity must be a whole
  * number of steps (to 1e-9 n_steps), else LV_ERR_STEP.  Path p (0 <= p <
  * n_paths) consumes Philox counter words (m, p) for m = 0 .. ceil(n_steps/4)-1
- * only, so results for any path are reproducible in isolation.
+ * only, so results for any path are reproducible in isolation.  Limits:
+ * n_steps <= 1e6, spot nodes x time nodes <= 1e5, n_steps x spot nodes <= 2^26
+ * (the per-step vol table), at most 256 options; beyond them LV_ERR_ARG or
+ * LV_ERR_UNSUPPORTED.
  *
  * Conventions: all functions return an lv_status; on failure the context's
  * message (lv_last_error) says why and no output has been written.  "Host"
@@ -102,7 +105,9 @@ typedef struct {
     int32_t block;          /* threads per block, a multiple of 64 in [64, 1024]; 0 = tuned default */
     int32_t blocks_per_cu;  /* persistent blocks per compute unit; 0 = tuned default */
     int32_t copies;         /* privatised copies of the LDS gradient histogram (1..16); 0 = default */
-    int32_t window;         /* steps per LDS table/histogram window (multiple of 4); 0 = default */
+    int32_t window;         /* steps per LDS vol-table window (multiple of 4 in [4, 64]); the gradient
+                               histogram spans the largest multiple of it that the LDS budget of
+                               blocks_per_cu blocks allows (up to the whole horizon); 0 = default */
     int32_t profile;        /* 1: time every kernel with hipEvents (eager launches only), read back
                                with lv_kernel_times */
     int32_t autotune;       /* 1: on the first call of a shape (grid, steps, paths, book size,
@@ -205,13 +210,14 @@ typedef struct {
     int32_t precision;
     int32_t graph_replayed;     /* 1 if the last call replayed a captured graph */
     int32_t copies;             /* histogram copies of the launch */
-    int32_t window;             /* steps per LDS window (the segment for the checkpoint kernel) */
+    int32_t window;             /* steps per LDS table window (the segment for the checkpoint kernel) */
     int32_t blocks_per_cu;      /* persistent blocks per CU asked for */
     int32_t autotuned;          /* 1 if the shape came from the autotuner */
     int32_t fwd_block;          /* threads per block of the separate forward kernel */
     int32_t fwd_blocks_per_cu;  /* its blocks per CU asked for */
     int32_t fwd_blocks;         /* its grid (its payoff partials are records 0 .. fwd_blocks-1) */
     int64_t overflow_terms;     /* reserved: 0 */
+    int32_t hist_window;        /* steps per gradient-histogram window (a multiple of window) */
 } lv_run_info;
 
 /* The launch shapes the autotuner would time for this request, as rows of
@@ -228,7 +234,7 @@ lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t
 lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info);
 
 /* Kernel kinds timed when lv_opts.profile is set. */
-enum { LV_K_FWD = 0, LV_K_REV = 1, LV_K_FUSED = 2, LV_K_MERGE = 3, LV_K_ZERO = 4, LV_K_COUNT = 5 };
+enum { LV_K_FWD = 0, LV_K_REV = 1, LV_K_FUSED = 2, LV_K_MERGE = 3, LV_K_TABLE = 4, LV_K_COUNT = 5 };
 
 /* Accumulated device time (ms, from hipEvents on the context's stream) and launch
  * counts per kernel kind, over all profiled calls since the last reset; waits

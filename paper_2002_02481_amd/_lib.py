@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "LV_OK", 1: "LV_ERR_ARG", 2: "LV_ERR_GRID", 3: "LV_ERR_STEP",
                 5: "LV_ERR_HIP", 6: "LV_ERR_UNSUPPORTED"}
 LV_AXIS_LIN, LV_AXIS_LOG = 0, 1
 LV_ADJ_DEFAULT, LV_ADJ_NONE, LV_ADJ_STORED, LV_ADJ_CHECKPOINT = 0, 1, 2, 3
-KERNEL_KINDS = ("fwd", "rev", "fused", "merge", "zero")
+KERNEL_KINDS = ("fwd", "rev", "fused", "merge", "table")
 ADJOINT = {"default": 0, "none": 1, "stored": 2, "checkpoint": 3}
 
 
@@ -51,7 +51,7 @@ class lv_run_info(C.Structure):
                 ("adjoint", C.c_int32), ("precision", C.c_int32), ("graph_replayed", C.c_int32),
                 ("copies", C.c_int32), ("window", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("autotuned", C.c_int32), ("fwd_block", C.c_int32), ("fwd_blocks_per_cu", C.c_int32),
-                ("fwd_blocks", C.c_int32), ("overflow_terms", C.c_int64)]
+                ("fwd_blocks", C.c_int32), ("overflow_terms", C.c_int64), ("hist_window", C.c_int32)]
 
 
 class LVError(RuntimeError):

@@ -38,10 +38,10 @@ struct Plan {
     long long P = 0;
     uint64_t seed = 0;
     int n_opt = 0, n_taps = 0;
-    std::vector<int> tj, tap_step, tap_first, tap_count, opt_put, opt_orig;
+    std::vector<int> tj, cell_lo, tap_step, tap_first, tap_count, opt_put, opt_orig;
     std::vector<double> ta, opt_strike, weight;
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;
-    int block = 256, blocks = 0, n_tiles = 0, W = 16, K = 8, S = 32, bpc = 2;
+    int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, S = 32, bpc = 2;
     int fblock = 256, fblocks = 0, f_n_tiles = 0, fbpc = 2;
     int G = 0, Q = 0;
     Shape user{0, 0, 0, 0, 0, 0};   // caller-fixed shape fields (0 = free)
@@ -57,7 +57,7 @@ struct lv_ctx {
     int n_cu = 256;
     size_t max_lds = 65536;
     std::string err = "no error";
-    Buf planbuf, part, seg, states, ckpt, sig_stage, out_stage;
+    Buf planbuf, part, seg, states, ckpt, sig_stage, out_stage, gtab;
     std::vector<char> plan_bytes;     // what planbuf holds
     lv_run_info info{};
     int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
@@ -131,12 +131,38 @@ int floor_pow2(long long x) {
     return p;
 }
 
-size_t lds_need(const Plan &pl, const Shape &sh) {
+// Table window of the adjoint (or fused) kernel: the checkpoint segment for the
+// fused kernel.
+int table_window(const Plan &pl, const Shape &sh) { return pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W; }
+
+size_t lds_adj(const Plan &pl, const Shape &sh, int WH) {
     const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
-    const int W = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W;
-    size_t a = lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, W, sh.K);
-    size_t b = lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, sh.fblock, W, sh.K);
-    return std::max(a, b);
+    return lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, table_window(pl, sh), WH, sh.K);
+}
+
+size_t lds_fwd(const Plan &pl, const Shape &sh) {
+    return lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, sh.fblock, table_window(pl, sh), 0,
+                          sh.K);
+}
+
+// Whether the shape fits the CU's LDS with the smallest histogram window.
+bool shape_fits(const Plan &pl, const Shape &sh, size_t max_lds) {
+    return lds_adj(pl, sh, table_window(pl, sh)) <= max_lds && lds_fwd(pl, sh) <= max_lds;
+}
+
+// Histogram window: the largest multiple of the table window (up to the whole
+// horizon) whose block still leaves room for the blocks per CU the shape asks
+// for (at most 2048 lanes per CU).  Fewer windows mean fewer folds.
+int hist_window(const Plan &pl, const Shape &sh, size_t max_lds) {
+    const int W = table_window(pl, sh);
+    const long long whole = ((long long)pl.N + W - 1) / W * W;
+    const int resident = std::max(1, std::min(sh.bpc, 2048 / sh.block));
+    const size_t budget = max_lds / resident;
+    const size_t base = lds_adj(pl, sh, 0);
+    const size_t per_step = (size_t)pl.I * sh.K * (pl.precision == 64 ? 8 : 4);
+    long long wh = budget > base ? (long long)((budget - base) / per_step) / W * W : 0;
+    wh = std::max<long long>(W, std::min(wh, whole));
+    return (int)wh;
 }
 
 // Defaults from launch-shape sweeps on MI355X: 1024-lane blocks with 2 histogram
@@ -147,27 +173,27 @@ Shape default_shape(const Plan &pl, int n_cu) {
     sh.block = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(pl.P / n_cu)));
     sh.K = 2;
     sh.W = 32;
-    sh.bpc = 2;
+    sh.bpc = 1;
     sh.fblock = (int)std::min<long long>(512, std::max<long long>(64, floor_pow2(pl.P / (2 * n_cu))));
     sh.fbpc = 4;
     return sh;
 }
 
-// Fix a shape into the plan, shrinking the window, then the copies (unless the
-// caller fixed them) until a block fits in 64 KiB of LDS (several blocks per CU);
-// beyond that up to the CU's whole LDS.
+// Fix a shape into the plan.  If a block does not fit the CU's LDS even with the
+// smallest histogram window, the table window, then the copies, are shrunk
+// (unless the caller fixed them).
 lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds, bool may_shrink_k,
                       bool may_shrink_w) {
-    const size_t soft = std::min<size_t>(max_lds, 65536);
-    while (lds_need(pl, sh) > soft && sh.W > 8 && may_shrink_w && pl.adjoint != LV_ADJ_CHECKPOINT) sh.W /= 2;
-    while (lds_need(pl, sh) > soft && sh.K > 1 && may_shrink_k) sh.K /= 2;
-    while (lds_need(pl, sh) > soft && sh.W > 4 && may_shrink_w && pl.adjoint != LV_ADJ_CHECKPOINT) sh.W /= 2;
-    if (lds_need(pl, sh) > max_lds)
+    const bool ckpt = pl.adjoint == LV_ADJ_CHECKPOINT;
+    while (!shape_fits(pl, sh, max_lds) && sh.W > 4 && may_shrink_w && !ckpt) sh.W /= 2;
+    while (!shape_fits(pl, sh, max_lds) && sh.K > 1 && may_shrink_k) sh.K /= 2;
+    if (!shape_fits(pl, sh, max_lds))
         return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)",
-                    lds_need(pl, sh), max_lds);
+                    std::max(lds_adj(pl, sh, table_window(pl, sh)), lds_fwd(pl, sh)), max_lds);
     pl.block = sh.block;
     pl.K = sh.K;
-    pl.W = pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W;
+    pl.W = table_window(pl, sh);
+    pl.WH = hist_window(pl, sh, max_lds);
     pl.bpc = sh.bpc;
     pl.n_tiles = (int)((pl.P + pl.block - 1) / pl.block);
     pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * sh.bpc);
@@ -194,7 +220,7 @@ std::vector<Shape> forward_candidates(const Plan &pl, const Shape &base, int n_c
             Shape sh = base;
             sh.fblock = b;
             sh.fbpc = c;
-            if (lds_need(pl, sh) > std::min<size_t>(max_lds, 65536)) continue;
+            if (!shape_fits(pl, sh, max_lds)) continue;
             out.push_back(sh);
         }
     }
@@ -215,7 +241,7 @@ std::vector<Shape> adjoint_candidates(const Plan &pl, const Shape &base, int n_c
                     sh.K = k;
                     sh.W = w;
                     sh.bpc = c;
-                    if (lds_need(pl, sh) > std::min<size_t>(max_lds, 65536)) continue;
+                    if (!shape_fits(pl, sh, max_lds)) continue;
                     out.push_back(sh);
                 }
             }
@@ -250,6 +276,9 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     if (book->n_opt > 256) return fail(ctx, LV_ERR_UNSUPPORTED, "at most 256 options per book (got %d)", book->n_opt);
     if (n_paths < 2 || n_paths > (1ll << 40)) return fail(ctx, LV_ERR_ARG, "n_paths must be in [2, 2^40]");
     if (n_steps < 1 || n_steps > 1000000) return fail(ctx, LV_ERR_ARG, "n_steps must be in [1, 1e6]");
+    if ((long long)n_steps * sa.n > (1ll << 26))
+        return fail(ctx, LV_ERR_UNSUPPORTED, "n_steps x spot nodes = %lld exceeds the vol table limit 2^26",
+                    (long long)n_steps * sa.n);
     if (n_surf < 1) return fail(ctx, LV_ERR_ARG, "n_surf must be >= 1");
     lv_opts o{};
     if (opts) o = *opts;
@@ -344,6 +373,10 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
         pl.tj[n] = j;
         pl.ta[n] = b - j;
     }
+    // first step of every time cell (t_n increases, so a cell's steps are contiguous)
+    pl.cell_lo.assign(ta.n, n_steps);
+    for (int n = 0, jn = 0; n < n_steps; ++n)
+        while (jn <= pl.tj[n]) pl.cell_lo[jn++] = n;
 
     // launch shape: explicit options win; otherwise the tuned shape (autotune)
     // or the default heuristics
@@ -383,7 +416,7 @@ int host_fixed_point_bits(const Plan &pl) {
 
 // Pack the plan's device tables; upload only when they change.
 struct Tables {
-    const int *tj, *tap_step, *tap_first, *tap_count, *opt_put, *opt_orig;
+    const int *tj, *cell_lo, *tap_step, *tap_first, *tap_count, *opt_put, *opt_orig;
     const double *ta, *opt_strike, *weight;
 };
 
@@ -396,8 +429,9 @@ void put(std::vector<char> &v, const std::vector<T> &x, size_t &off) {
 
 lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
     std::vector<char> v;
-    size_t o[9];
+    size_t o[10];
     put(v, pl.tj, o[0]);
+    put(v, pl.cell_lo, o[9]);
     put(v, pl.tap_step, o[1]);
     put(v, pl.tap_first, o[2]);
     put(v, pl.tap_count, o[3]);
@@ -416,6 +450,7 @@ lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
     }
     char *b = (char *)ctx->planbuf.p;
     t.tj = (const int *)(b + o[0]);
+    t.cell_lo = (const int *)(b + o[9]);
     t.tap_step = (const int *)(b + o[1]);
     t.tap_first = (const int *)(b + o[2]);
     t.tap_count = (const int *)(b + o[3]);
@@ -427,7 +462,7 @@ lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
     return LV_OK;
 }
 
-lvk::Args make_args(const Plan &pl, const Tables &t, const double *sigma_dev) {
+lvk::Args make_args(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *sigma_dev) {
     lvk::Args a{};
     a.I = pl.I;
     a.J = pl.J;
@@ -441,6 +476,8 @@ lvk::Args make_args(const Plan &pl, const Tables &t, const double *sigma_dev) {
     a.sigma = sigma_dev;
     a.tj = t.tj;
     a.ta = t.ta;
+    a.cell_lo = t.cell_lo;
+    a.gtab = ctx->gtab.p;
     a.P = pl.P;
     a.key0 = (unsigned)(pl.seed & 0xFFFFFFFFu);
     a.key1 = (unsigned)(pl.seed >> 32);
@@ -456,6 +493,7 @@ lvk::Args make_args(const Plan &pl, const Tables &t, const double *sigma_dev) {
     a.Q = pl.Q;
     a.n_tiles = pl.n_tiles;
     a.W = pl.W;
+    a.WH = pl.WH;
     a.K = pl.K;
     a.seg = pl.seg;
     return a;
@@ -463,9 +501,15 @@ lvk::Args make_args(const Plan &pl, const Tables &t, const double *sigma_dev) {
 
 size_t real_bytes(int precision) { return precision == 64 ? 8 : 4; }
 
+// The per-step vol table every pricing kernel reads.
+lv_status ensure_table(lv_ctx *ctx, const Plan &pl) {
+    return ensure(ctx, ctx->gtab, (size_t)pl.N * pl.I * 2 * real_bytes(pl.precision));
+}
+
 // Workspace for the fused paths.
 lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
     lv_status st;
+    if ((st = ensure_table(ctx, pl)) != LV_OK) return st;
     if ((st = ensure(ctx, ctx->part, (size_t)std::max(pl.blocks, pl.fblocks) * pl.Q * 8)) != LV_OK) return st;
     if ((st = ensure(ctx, ctx->seg, (size_t)pl.S * pl.Q * 8)) != LV_OK) return st;
     if (adjoint && pl.adjoint == LV_ADJ_STORED) {
@@ -527,12 +571,13 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
                            bool adjoint, double *price, double *stderr_, double *grad,
                            double *delta, bool capturing) {
     hipStream_t st = ctx->stream();
-    lvk::Args a = make_args(pl, t, sigma_dev);
+    lvk::Args a = make_args(ctx, pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
     a.states = ctx->states.p;
     a.ckpt = ctx->ckpt.p;
     const bool prof = pl.profile && !capturing;
-    hipError_t e;
+    hipError_t e = timed(ctx, prof, LV_K_TABLE, [&] { return lvk::launch_table(a, pl.precision, st); });
+    if (e != hipSuccess) return e;
     lvk::Args af = a;                 // the forward kernel's own tiling
     af.n_tiles = pl.f_n_tiles;
     if (!adjoint) {
@@ -582,14 +627,15 @@ void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
     ctx->info.fwd_blocks_per_cu = pl.fbpc;
     ctx->info.fwd_blocks = pl.fblocks;
     ctx->info.overflow_terms = 0;
+    ctx->info.hist_window = pl.WH;
 }
 
 std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf, bool adjoint) {
     std::string k;
     char buf[128];
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I, pl.J,
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I, pl.J,
              pl.N, pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
-             pl.blocks, pl.W, pl.K, pl.fblock, pl.fblocks, pl.spot, pl.dt, n_surf);
+             pl.blocks, pl.W, pl.WH, pl.K, pl.fblock, pl.fblocks, pl.spot, pl.dt, n_surf);
     k += buf;
     k += adjoint ? "A|" : "F|";
     for (int i = 0; i < n_ptrs; ++i) {
@@ -710,8 +756,8 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
         return LV_OK;
     }
     const void *ptrs[] = {sigmas_dev, prices, stderrs, grads, deltas, ctx->planbuf.p, ctx->part.p,
-                          ctx->seg.p, ctx->states.p, ctx->ckpt.p};
-    std::string key = graph_key(pl, ptrs, 10, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
+                          ctx->seg.p, ctx->states.p, ctx->ckpt.p, ctx->gtab.p};
+    std::string key = graph_key(pl, ptrs, 11, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
     bool replay = ctx->graph_exec && key == ctx->graph_key;
     if (!replay) {
         if (ctx->graph_exec) {
@@ -788,7 +834,7 @@ void lv_destroy(lv_ctx *ctx) {
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->seg, &ctx->states, &ctx->ckpt,
-                   &ctx->sig_stage, &ctx->out_stage};
+                   &ctx->sig_stage, &ctx->out_stage, &ctx->gtab};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -808,7 +854,7 @@ const char *lv_last_error(const lv_ctx *ctx) {
 lv_status lv_check(const lv_grid *grid, const double *sigma, double spot, const lv_book *book,
                    int64_t n_paths, int32_t n_steps, const lv_opts *opts) {
     Plan pl;
-    return plan_request(nullptr, grid, 1, sigma, spot, book, n_paths, n_steps, 0, opts, 256, 65536, pl);
+    return plan_request(nullptr, grid, 1, sigma, spot, book, n_paths, n_steps, 0, opts, 256, 160 * 1024, pl);
 }
 
 lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
@@ -902,11 +948,12 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
     if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
     if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
     hipStream_t st = ctx->stream();
-    lvk::Args a = make_args(pl, t, sigma_dev);
+    lvk::Args a = make_args(ctx, pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
     a.states = states_dev;
     a.n_tiles = pl.f_n_tiles;
-    hipError_t e = lvk::launch_fwd(a, pl.precision, true, pl.fblocks, pl.fblock, st);
+    hipError_t e = lvk::launch_table(a, pl.precision, st);
+    if (e == hipSuccess) e = lvk::launch_fwd(a, pl.precision, true, pl.fblocks, pl.fblock, st);
     if (e == hipSuccess)
         e = lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
                               pl.G, t.opt_orig, pl.P, pl.spot, price_dev, std_err_dev, nullptr, nullptr, st);
@@ -935,12 +982,13 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
     if ((s = ensure(ctx, ctx->out_stage, (size_t)2 * pl.n_opt * 8)) != LV_OK) return s;
     hipStream_t st = ctx->stream();
-    lvk::Args a = make_args(pl, t, sigma_dev);
+    lvk::Args a = make_args(ctx, pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
     a.states = const_cast<void *>(states_dev);
     a.cot = cotangent_dev;
     // the reverse writes no payoff sums: the merge's price outputs go to scratch
-    hipError_t e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
+    hipError_t e = lvk::launch_table(a, pl.precision, st);
+    if (e == hipSuccess) e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
     double *scratch = (double *)ctx->out_stage.p;
     if (e == hipSuccess)
         e = lvk::launch_merge(a.part, pl.blocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,

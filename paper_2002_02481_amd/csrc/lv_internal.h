@@ -17,8 +17,11 @@ struct Args {
     double a_off;               // grid coordinate a = x * inv_du + a_off (x = S on lin, y on log)
     double spot, dt, sqrt_dt;
     const double *sigma;        // [I][J] FP64, this surface
-    const int *tj;              // [N] time cell of step n
+    const int *tj;              // [N] time cell of step n (non-decreasing in n)
     const double *ta;           // [N] weight of time node tj+1 at step n
+    const int *cell_lo;         // [J] first step whose time cell is >= j (N if none)
+    const void *gtab;           // [N][I] pairs (c, d) in the kernel's precision: c = sigma(x_i, t_n)
+                                // time-interpolated, d = c(x_{i+1}) - c(x_i) (0 at the last node)
     long long P;                // paths
     unsigned key0, key1;        // Philox key = seed
     // book
@@ -38,23 +41,26 @@ struct Args {
     int Q;
     // tiling
     int n_tiles;                // path tiles of blockDim paths
-    int W;                      // steps per LDS window (multiple of 4)
+    int W;                      // steps per LDS table window (multiple of 4)
+    int WH;                     // steps per gradient-histogram window (multiple of W)
     int K;                      // privatised histogram copies
     int seg;                    // checkpoint segment (steps)
 };
 
 enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };
 
-// LDS bytes a kernel variant needs for the given shape.
-size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int K);
+// LDS bytes a kernel variant needs for the given shape (W table steps, WH
+// histogram steps).
+size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K);
 // Largest fixed-point term the gradient histogram accepts, for the given shape.
 __host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P);
 
+// Vol table of every step into a.gtab (run before the pricing kernels).
+hipError_t launch_table(const Args &a, int precision, hipStream_t st);
 hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block,
                       hipStream_t st);
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st);
 hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st);
-hipError_t launch_zero(double *p, size_t n, hipStream_t st);
 // Fixed-order merge of part [records][Q] into final outputs: payoff entries over
 // the first B_pay records, the rest over the first B_grad.
 hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, double *seg, int S,

@@ -6,20 +6,23 @@
 //
 // Mapping: one lane per path, 64-lane wavefronts, blocks of whole wavefronts that
 // loop over path tiles (persistent grid).  All lanes of a block are at the same
-// step, so the time cell of a step is uniform: each block stages, per window of
-// W steps, a table in LDS of the time-interpolated vol column and its
-// node-to-node difference, c[n][i] = sigma(x_i, t_n), d[n][i] = c[n][i+1] - c[n][i];
-// the spot lookup is then one 8- or 16-byte LDS read and one FMA.
+// step, so the time cell of a step is uniform.  A small kernel first writes, for
+// every step, the time-interpolated vol column and its node-to-node difference,
+// c[n][i] = sigma(x_i, t_n), d[n][i] = c[n][i+1] - c[n][i]; blocks copy windows of
+// W steps of it into LDS (double-buffered, the next window's copy in flight while
+// the current one is used), so the spot lookup is one LDS read and one FMA.
 //
 // Gradient accumulation: per step a path adds x(1-f) to spot node i and x f to
 // node i+1 of that step's column (x = lambda * dy_{n+1}/dsigma_n), the time
 // weights being uniform.  LDS float atomics are slow on gfx950, integer ones are
 // not, so the two terms are rounded to fixed point (scale 2^F chosen from the
 // book's size) and added with ds_add_u32 (FP32 kernels) or ds_add_u64 (FP64
-// kernels) into a per-window histogram H[w][i][copy], privatised K ways by lane
-// to spread same-cell collisions.  At each window boundary the owner thread of
-// spot node i folds H into a per-block FP64 grid with the time weights; blocks
-// write their grids once and a fixed-order compensated merge combines them.
+// kernels) into a step-indexed histogram H[n][i][copy], privatised K ways by lane
+// to spread same-cell collisions.  The histogram spans WH steps (as many as fit,
+// often the whole horizon); at its boundaries and at the end of a path tile it is
+// folded into a per-block FP64 grid with the time weights, one owner thread per
+// grid node.  Blocks write their grids once and a fixed-order compensated merge
+// combines them.
 // Terms too large for the fixed-point range take an FP64 LDS-atomic side path into
 // the block's grid.
 #include <hip/hip_runtime.h>
@@ -125,67 +128,121 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 // LDS carve-up, shared by the kernels and the host planner.
 // --------------------------------------------------------------------------
 struct Lds {
-    size_t g64, wpart, wlam, fbuf, tab, hist, total;
+    size_t g64, wpart, wlam, tab, hist, total;
 };
 
 __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes, int I, int J,
-                                          int n_opt, int wpb, int W, int K) {
+                                          int n_opt, int wpb, int W, int WH, int K) {
     Lds L{};
     size_t off = 0;
     const bool grad = variant == REV_STORED || variant == FUSED_CKPT;
     const bool pay = variant != REV_STORED;
+    const int tab_bufs = variant == FUSED_CKPT ? 1 : 2;   // double-buffered where prefetched
     L.g64 = off;
     off += grad ? align16((size_t)I * J * 8) : 0;
     L.wpart = off;
     off += pay ? align16((size_t)wpb * n_opt * 2 * 8) : 0;
     L.wlam = off;
     off += grad ? align16((size_t)wpb * 8) : 0;
-    L.fbuf = off;
-    off += grad ? align16((size_t)W * I * 8) : 0;
     L.tab = off;
-    off += align16((size_t)W * I * 2 * rbytes);
+    off += align16((size_t)tab_bufs * W * I * 2 * rbytes);
     L.hist = off;
-    off += grad ? align16((size_t)W * I * K * accbytes) : 0;
+    off += grad ? align16((size_t)WH * I * K * accbytes) : 0;
     L.total = off;
     return L;
 }
 
-size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int K) {
+size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K) {
     const int rb = precision == 64 ? 8 : 4;
-    return lds_layout(variant, rb, rb, I, J, n_opt, block / 64, W, K).total;
+    return lds_layout(variant, rb, rb, I, J, n_opt, block / 64, W, WH, K).total;
 }
 
 __host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P) {
     // Lanes with a path: at most min(block, P).  FP32: every histogram word receives
-    // at most one term per path of its copy class per window and must stay inside
-    // int32.  FP64: the K words of a node are summed in int64 at the fold, so all of
-    // a block's terms must fit.
+    // at most one term per path of its copy class between folds (one tile) and must
+    // stay inside int32.  FP64: the K words of a node are summed in int64 at the
+    // fold, so all of a tile's terms must fit.
     const int act = (int)(P < block ? P : block);
     if (precision == 64) return ldexp(1.0, 62) / act;
     return floor(2147483000.0 / (double)((act + K - 1) / K)) - 2.0;
 }
 
 // --------------------------------------------------------------------------
-// Device building blocks
+// Vol table of every step: c = sigma(x_i, t_n), d = c(x_{i+1}) - c(x_i), time-
+// interpolated in FP64 and rounded once to the kernel precision.
 // --------------------------------------------------------------------------
-// Table of steps n0 .. n0+nw-1: c = sigma(x_i, t_n), d = c(x_{i+1}) - c(x_i),
-// time-interpolated in FP64 and rounded once.
 template <typename R>
-__device__ void build_table(R *tab, const Args &a, int n0, int nw) {
+__global__ void k_table(Args a) {
     const int I = a.I, J = a.J;
-    for (int e = threadIdx.x; e < nw * I; e += blockDim.x) {
-        const int w = e / I, i = e - w * I, n = n0 + w;
+    const long long ne = (long long)a.N * I;
+    R *t = (R *)const_cast<void *>(a.gtab);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(e / I), i = (int)(e - (long long)n * I);
         const int j = a.tj[n];
         const double al = a.ta[n];
         const double *s = a.sigma;
         const double c0 = (1.0 - al) * s[i * J + j] + al * s[i * J + j + 1];
         double c1 = c0;
         if (i + 1 < I) c1 = (1.0 - al) * s[(i + 1) * J + j] + al * s[(i + 1) * J + j + 1];
-        tab[2 * e] = (R)c0;
-        tab[2 * e + 1] = (R)(c1 - c0);
+        t[2 * e] = (R)c0;
+        t[2 * e + 1] = (R)(c1 - c0);
     }
 }
 
+// --------------------------------------------------------------------------
+// Table windows.  Rows n0 .. n0+nw-1 of the global table are contiguous, so a
+// window is a straight copy into LDS.  issue() loads the first PF pairs per
+// thread into registers, commit() writes them (and copies any remainder) into
+// an LDS buffer; the forward and reverse kernels issue the next window's copy
+// at a window start and commit it one step group later into the other buffer.
+// --------------------------------------------------------------------------
+template <typename R>
+struct Pair;
+template <>
+struct Pair<float> {
+    typedef float2 T;
+    static constexpr int PF = 4;
+};
+template <>
+struct Pair<double> {
+    typedef double2 T;
+    static constexpr int PF = 2;
+};
+
+template <typename R>
+struct TabStage {
+    typedef typename Pair<R>::T T;
+    static constexpr int PF = Pair<R>::PF;
+    T v[PF];
+    int n0, nw;
+    __device__ __forceinline__ void issue(const Args &a, int first, int count) {
+        n0 = first;
+        nw = count;
+        const T *src = (const T *)a.gtab + (size_t)n0 * a.I;
+        const int ne = nw * a.I;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int e = threadIdx.x + k * blockDim.x;
+            if (e < ne) v[k] = src[e];
+        }
+    }
+    __device__ __forceinline__ void commit(const Args &a, R *dst) const {
+        const T *src = (const T *)a.gtab + (size_t)n0 * a.I;
+        T *d = (T *)dst;
+        const int ne = nw * a.I;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int e = threadIdx.x + k * blockDim.x;
+            if (e < ne) d[e] = v[k];
+        }
+        for (int e = threadIdx.x + PF * blockDim.x; e < ne; e += blockDim.x) d[e] = src[e];
+    }
+};
+
+// --------------------------------------------------------------------------
+// Device building blocks
+// --------------------------------------------------------------------------
 __device__ __forceinline__ float clamp_to(float a, float hi) {
     return __builtin_amdgcn_fmed3f(a, 0.0f, hi);
 }
@@ -263,52 +320,51 @@ __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam) {
     return lam;
 }
 
-// Fold of a window's histogram into the block's FP64 grid, in two stages.
-// Stage 1 (all threads): F[w][i] = sum over copies of H[w][i][.] * 2^-F, H cleared.
+// Fold of the histogram rows of steps [h0, h0 + nh) into the block's FP64 grid.
+// Node (i, j) takes alpha_n of every row n of time cell j - 1 and 1 - alpha_n of
+// every row of cell j (the steps of a cell are contiguous), so each node has one
+// owner thread and no atomics are needed; the rows are then cleared.  Callers
+// synchronise the block before; it is synchronised again on return.
 template <typename R>
-__device__ void fold1(const Args &a, typename Math<R>::Acc *H, double *Fb, int nw, double inv_sc) {
-    const int I = a.I, K = a.K;
-    for (int e = threadIdx.x; e < nw * I; e += blockDim.x) {
-        typename Math<R>::Acc *h = H + (size_t)e * K;
-        long long s = 0;
-        for (int c = 0; c < K; ++c) {
-            s += (long long)h[c];
-            h[c] = 0;
-        }
-        Fb[e] = (double)s * inv_sc;
-    }
-}
-
-// Stage 2 (owner thread of spot node i): spread F[w][i] over time nodes j_w and
-// j_w + 1 with weights 1 - alpha_w and alpha_w, holding runs of equal j in registers.
-__device__ void fold2(const Args &a, const double *Fb, double *g64, int w0, int nw) {
-    const int I = a.I, J = a.J;
-    for (int i = threadIdx.x; i < I; i += blockDim.x) {
-        int jc = -1;
-        double a0 = 0.0, a1 = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            const int n = w0 + w, j = a.tj[n];
-            const double al = a.ta[n], v = Fb[w * I + i];
-            if (j != jc) {
-                if (jc >= 0) {
-                    g64[i * J + jc] += a0;
-                    g64[i * J + jc + 1] += a1;
-                }
-                jc = j;
-                a0 = a1 = 0.0;
+__device__ void fold(const Args &a, typename Math<R>::Acc *H, double *g64, int h0, int nh,
+                     double inv_sc) {
+    typedef typename Math<R>::Acc Acc;
+    const int I = a.I, J = a.J, K = a.K, h1 = h0 + nh;
+    const int c0 = a.tj[h0], c1 = a.tj[h1 - 1];
+    const int nn = (c1 - c0 + 2) * I;   // nodes j = c0 .. c1 + 1
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int jj = e / I, i = e - jj * I, j = c0 + jj;
+        double acc = 0.0;
+        if (j > c0) {
+            const int lo = max(a.cell_lo[j - 1], h0), hi = min(a.cell_lo[j], h1);
+            for (int n = lo; n < hi; ++n) {
+                const Acc *h = H + ((size_t)(n - h0) * I + i) * K;
+                long long q = 0;
+                for (int c = 0; c < K; ++c) q += (long long)h[c];
+                acc += a.ta[n] * ((double)q * inv_sc);
             }
-            a0 += (1.0 - al) * v;
-            a1 += al * v;
         }
-        if (jc >= 0) {
-            g64[i * J + jc] += a0;
-            g64[i * J + jc + 1] += a1;
+        if (j <= c1) {
+            const int lo = max(a.cell_lo[j], h0), hi = min(a.cell_lo[j + 1], h1);
+            for (int n = lo; n < hi; ++n) {
+                const Acc *h = H + ((size_t)(n - h0) * I + i) * K;
+                long long q = 0;
+                for (int c = 0; c < K; ++c) q += (long long)h[c];
+                acc += (1.0 - a.ta[n]) * ((double)q * inv_sc);
+            }
         }
+        g64[i * J + j] += acc;
     }
+    __syncthreads();
+    const size_t words = (size_t)nh * I * K, n16 = words * sizeof(Acc) / 16;
+    int4 *h4 = (int4 *)H;
+    for (size_t e = threadIdx.x; e < n16; e += blockDim.x) h4[e] = make_int4(0, 0, 0, 0);
+    for (size_t e = n16 * 16 / sizeof(Acc) + threadIdx.x; e < words; e += blockDim.x) H[e] = 0;
+    __syncthreads();
 }
 
 // Scatter of one step's adjoint term x = gb * 2^F: x(1-f) to node i and x f to
-// node i+1 of window row wn, in this lane's copy column Hl (= H + lane copy).
+// node i+1 of histogram row wn, in this lane's copy column Hl (= H + lane copy).
 template <typename R>
 __device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl, double *g64, int wn,
                                         int n, const Look<R> &L, R gb, R sc, R qm) {
@@ -351,47 +407,68 @@ template <typename R, int AXIS, bool STORE>
 __global__ void __launch_bounds__(1024) k_fwd(Args a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const Lds lay = lds_layout(STORE ? FWD_STORE : FWD_PRICE, sizeof(R), sizeof(R), a.I, a.J,
-                               a.n_opt, wpb, a.W, a.K);
+    const int I = a.I, N = a.N, W = a.W, nW = (N + W - 1) / W;
+    const Lds lay = lds_layout(STORE ? FWD_STORE : FWD_PRICE, sizeof(R), sizeof(R), I, a.J, a.n_opt,
+                               wpb, W, a.WH, a.K);
     double *wpart = (double *)(smem + lay.wpart);
-    R *tab = (R *)(smem + lay.tab);
+    R *tuse = (R *)(smem + lay.tab), *tnext = tuse + 2 * W * I;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
 
     const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
-    const R spot = (R)a.spot, amax = (R)(a.I - 1);
-    const int imax = a.I - 2, N = a.N, n_groups = (N + 3) >> 2;
+    const R spot = (R)a.spot, amax = (R)(I - 1);
+    const int imax = I - 2;
+    TabStage<R> stg;
+    int wcur = -1;
+    if ((int)blockIdx.x < a.n_tiles) {   // first window, into the buffer entered first
+        stg.issue(a, 0, min(W, N));
+        stg.commit(a, tnext);
+    }
 
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const bool more = tile + (int)gridDim.x < a.n_tiles;
         const long long p = (long long)tile * blockDim.x + tid;
         const bool active = p < a.P;
+        const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         R y = 0;
-        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1, wstart = 0;
-        for (int g = 0; g < n_groups; ++g) {
-            const int n0 = g << 2;
-            if (n0 % a.W == 0) {
-                __syncthreads();
-                build_table<R>(tab, a, n0, min(a.W, N - n0));
-                __syncthreads();
-                wstart = n0;
+        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
+        for (int wi = 0; wi < nW; ++wi) {
+            const int ws = wi * W, we = min(N, ws + W);
+            bool pending = false;
+            if (wi != wcur) {
+                __syncthreads();   // window wi is in tnext; nobody reads tuse any more
+                R *t = tuse;
+                tuse = tnext;
+                tnext = t;
+                wcur = wi;
+                const int nx = wi + 1 < nW ? wi + 1 : (more ? 0 : -1);
+                if (nx >= 0 && nW > 1) {
+                    stg.issue(a, nx * W, min(W, N - nx * W));
+                    pending = true;
+                }
             }
-            const Words w = philox10((uint32_t)g, 0u, (uint32_t)p, (uint32_t)((unsigned long long)p >> 32),
-                                     a.key0, a.key1);
-            R z[4];
-            Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
-            Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
+            for (int n0 = ws; n0 < we; n0 += 4) {
+                const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
+                R z[4];
+                Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
+                Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = n0 + r;
-                if (n < N) {
-                    const R *trow = tab + 2 * (n - wstart) * a.I;
-                    const Look<R> L = lookup<R, AXIS>(y, trow, inv_du, a_off, amax, imax, spot);
-                    y = fma(L.s, fma(-hdt, L.s, z[r]), y);
-                    if (STORE && active) ((R *)a.states)[(size_t)n * a.P + p] = y;
-                    if (n + 1 == next_tap) {
-                        fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
-                        ++tap;
-                        next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                for (int r = 0; r < 4; ++r) {
+                    const int n = n0 + r;
+                    if (n < N) {
+                        const R *trow = tuse + 2 * (n - ws) * I;
+                        const Look<R> L = lookup<R, AXIS>(y, trow, inv_du, a_off, amax, imax, spot);
+                        y = fma(L.s, fma(-hdt, L.s, z[r]), y);
+                        if (STORE && active) ((R *)a.states)[(size_t)n * a.P + p] = y;
+                        if (n + 1 == next_tap) {
+                            fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
+                            ++tap;
+                            next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                        }
                     }
+                }
+                if (pending) {
+                    stg.commit(a, tnext);
+                    pending = false;
                 }
             }
         }
@@ -409,23 +486,24 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
 // sqrt(dt) Z_n is recovered from the stored states as (y_{n+1} - y_n)/sigma_n
 // - sigma_n dt / 2, so no random numbers are drawn again.  Steps run in groups
 // of four: the four lookups first (they do not depend on lambda, so their LDS
-// reads overlap), then the lambda recursion and the histogram scatter.
+// reads overlap), then the lambda recursion and the histogram scatter.  Table
+// windows run last to first; the histogram is folded at histogram-window
+// boundaries and at the end of every tile.
 // --------------------------------------------------------------------------
 template <typename R, int AXIS>
 __global__ void __launch_bounds__(1024) k_rev(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int I = a.I, J = a.J, N = a.N, W = a.W, G = I * J;
-    const Lds lay = lds_layout(REV_STORED, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, W, a.K);
+    const int I = a.I, J = a.J, N = a.N, W = a.W, WH = a.WH, G = I * J, nW = (N + W - 1) / W;
+    const Lds lay = lds_layout(REV_STORED, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, W, WH, a.K);
     double *g64 = (double *)(smem + lay.g64);
     double *wlam = (double *)(smem + lay.wlam);
-    double *Fb = (double *)(smem + lay.fbuf);
-    R *tab = (R *)(smem + lay.tab);
+    R *tuse = (R *)(smem + lay.tab), *tnext = tuse + 2 * W * I;
     Acc *H = (Acc *)(smem + lay.hist);
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
-    for (int e = tid; e < W * I * a.K; e += blockDim.x) H[e] = 0;
+    for (int e = tid; e < WH * I * a.K; e += blockDim.x) H[e] = 0;
 
     const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K, a.P);
     const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
@@ -437,15 +515,22 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
     Acc *Hl = H + tid % K;               // this lane's copy column
     const R *Y = (const R *)a.states;
     const size_t P = (size_t)a.P;
+    TabStage<R> stg;
+    int wcur = -1;
+    if ((int)blockIdx.x < a.n_tiles) {   // last window, into the buffer entered first
+        stg.issue(a, (nW - 1) * W, N - (nW - 1) * W);
+        stg.commit(a, tnext);
+    }
 
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const bool more = tile + (int)gridDim.x < a.n_tiles;
         const long long p = (long long)tile * blockDim.x + tid;
         const bool active = p < a.P;
         const size_t pc = active ? (size_t)p : P - 1;     // inactive lanes read a valid path
         R lam = 0;
         R y_next = Y[(size_t)(N - 1) * P + pc];
         int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
-        int wcur = -1;
+        int hcur = (N - 1) / WH;
         // cur[r] = y_{4g+r} (plane 4g+r-1; y_0 = 0)
         R cur[4], nxt[4];
         {
@@ -456,73 +541,86 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
                 cur[r] = (n >= 1 && n <= N - 1) ? Y[(size_t)(n - 1) * P + pc] : (R)0;
             }
         }
-        for (int g = n_groups - 1; g >= 0; --g) {
-            const int n0 = g << 2, wi = n0 / W;
+        for (int wi = nW - 1; wi >= 0; --wi) {
+            const int ws = wi * W, we = min(N, ws + W);
+            bool pending = false;
             if (wi != wcur) {
-                __syncthreads();
-                if (wcur >= 0) {
-                    fold1<R>(a, H, Fb, min(W, N - wcur * W), inv_sc);
-                    __syncthreads();
-                    fold2(a, Fb, g64, wcur * W, min(W, N - wcur * W));
+                __syncthreads();   // window wi is in tnext; tuse and the histogram are idle
+                const int hi = ws / WH;
+                if (hi != hcur) {
+                    fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
+                    hcur = hi;
                 }
-                build_table<R>(tab, a, wi * W, min(W, N - wi * W));
-                __syncthreads();
+                R *t = tuse;
+                tuse = tnext;
+                tnext = t;
                 wcur = wi;
-            }
-            if (g > 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int n = 4 * (g - 1) + r;
-                    nxt[r] = n >= 1 ? Y[(size_t)(n - 1) * P + pc] : (R)0;
+                const int nx = wi > 0 ? wi - 1 : (more ? nW - 1 : -1);
+                if (nx >= 0 && nW > 1) {
+                    stg.issue(a, nx * W, min(W, N - nx * W));
+                    pending = true;
                 }
             }
-            const int wn0 = n0 - wi * W;
-            auto group = [&](auto full_tag) {
-                constexpr bool FULL = decltype(full_tag)::value;
-                Look<R> L[4];
-                R cc[4], dsd[4], yup[4];
+            const int hbase = hcur * WH;
+            for (int g = (we - 1) >> 2; g >= (ws >> 2); --g) {
+                const int n0 = g << 2;
+                if (g > 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (FULL || n0 + r < N) {
-                        yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : cur[r + 1];
-                        L[r] = lookup<R, AXIS>(cur[r], tab + 2 * (wn0 + r) * I, inv_du, a_off, amax,
-                                               imax, spot);
-                        cc[r] = (yup[r] - cur[r]) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
-                        R d = L[r].in ? L[r].d * inv_du : (R)0;
-                        if (AXIS == 0) d *= L[r].S;
-                        dsd[r] = d;
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = 4 * (g - 1) + r;
+                        nxt[r] = n >= 1 ? Y[(size_t)(n - 1) * P + pc] : (R)0;
                     }
                 }
+                const int wn0 = n0 - ws, hn0 = n0 - hbase;
+                auto group = [&](auto full_tag) {
+                    constexpr bool FULL = decltype(full_tag)::value;
+                    Look<R> L[4];
+                    R cc[4], dsd[4], yup[4];
 #pragma unroll
-                for (int r = 3; r >= 0; --r) {
-                    const int n = n0 + r;
-                    if (FULL || n < N) {
-                        if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R>(a, tap, yup[r], lam);
-                            if (!active) lam = 0;
-                            --tap;
-                            cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+                    for (int r = 0; r < 4; ++r) {
+                        if (FULL || n0 + r < N) {
+                            yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : cur[r + 1];
+                            L[r] = lookup<R, AXIS>(cur[r], tuse + 2 * (wn0 + r) * I, inv_du, a_off,
+                                                   amax, imax, spot);
+                            cc[r] = (yup[r] - cur[r]) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
+                            R d = L[r].in ? L[r].d * inv_du : (R)0;
+                            if (AXIS == 0) d *= L[r].S;
+                            dsd[r] = d;
                         }
-                        const R gb = lam * cc[r];
-                        lam = fma(lam * cc[r], dsd[r], lam);
-                        scatter<R>(a, Hl, g64, wn0 + r, n, L[r], gb, sc, qm);
                     }
-                }
-            };
-            if (n0 + 4 <= N)
-                group(std::true_type{});
-            else
-                group(std::false_type{});
-            y_next = cur[0];
-            if (g > 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cur[r] = nxt[r];
+                    for (int r = 3; r >= 0; --r) {
+                        const int n = n0 + r;
+                        if (FULL || n < N) {
+                            if (n + 1 == cur_tap) {
+                                lam = rev_seeds<R>(a, tap, yup[r], lam);
+                                if (!active) lam = 0;
+                                --tap;
+                                cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+                            }
+                            const R gb = lam * cc[r];
+                            lam = fma(lam * cc[r], dsd[r], lam);
+                            scatter<R>(a, Hl, g64, hn0 + r, n, L[r], gb, sc, qm);
+                        }
+                    }
+                };
+                if (n0 + 4 <= N)
+                    group(std::true_type{});
+                else
+                    group(std::false_type{});
+                y_next = cur[0];
+                if (g > 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cur[r] = nxt[r];
+                }
+                if (pending) {
+                    stg.commit(a, tnext);
+                    pending = false;
+                }
             }
         }
         __syncthreads();
-        fold1<R>(a, H, Fb, min(W, N - wcur * W), inv_sc);
-        __syncthreads();
-        fold2(a, Fb, g64, wcur * W, min(W, N - wcur * W));
+        fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
         const double l0 = wave_sum(active ? (double)lam : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
@@ -542,25 +640,27 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
 // reverse pass segment by segment (last first): the segment is re-simulated
 // from its checkpoint with the same Philox counters, its states and
 // c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and swept backwards.
-// Checkpoints live in per-block slots reused by every tile of the block.
+// Checkpoints live in per-block slots reused by every tile of the block.  The
+// LDS table holds one segment; consecutive uses of the same segment (the last
+// one forward then backward, the first one backward then forward for the next
+// tile) share its copy.
 // --------------------------------------------------------------------------
 template <typename R, int AXIS, int SEG>
 __global__ void __launch_bounds__(1024) k_fused(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int I = a.I, J = a.J, N = a.N, G = I * J;
-    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, a.K);
+    const int I = a.I, J = a.J, N = a.N, G = I * J, WH = a.WH;
+    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, WH, a.K);
     double *g64 = (double *)(smem + lay.g64);
     double *wpart = (double *)(smem + lay.wpart);
     double *wlam = (double *)(smem + lay.wlam);
-    double *Fb = (double *)(smem + lay.fbuf);
     R *tab = (R *)(smem + lay.tab);
     Acc *H = (Acc *)(smem + lay.hist);
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
-    for (int e = tid; e < SEG * I * a.K; e += blockDim.x) H[e] = 0;
+    for (int e = tid; e < WH * I * a.K; e += blockDim.x) H[e] = 0;
 
     const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K, a.P);
     const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
@@ -573,6 +673,8 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
     R *CK = (R *)a.ckpt;
     const size_t slot_stride = (size_t)gridDim.x * blockDim.x;
     const size_t slot = (size_t)blockIdx.x * blockDim.x + tid;
+    TabStage<R> stg;
+    int tcur = -1;   // segment whose table is in LDS
 
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const long long p = (long long)tile * blockDim.x + tid;
@@ -584,9 +686,13 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
             CK[(size_t)sg * slot_stride + slot] = y;
-            __syncthreads();
-            build_table<R>(tab, a, na, nw);
-            __syncthreads();
+            if (sg != tcur) {
+                __syncthreads();
+                stg.issue(a, na, nw);
+                stg.commit(a, tab);
+                __syncthreads();
+                tcur = sg;
+            }
 #pragma unroll
             for (int q4 = 0; q4 < SEG / 4; ++q4) {
                 const int n0 = na + 4 * q4;
@@ -615,16 +721,22 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
         // ---- reverse, segment by segment
         R lam = 0, y_next = y;
         int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+        int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
-            __syncthreads();
-            if (sg < n_seg - 1) {
-                fold1<R>(a, H, Fb, min(SEG, N - na - SEG), inv_sc);
-                __syncthreads();
-                fold2(a, Fb, g64, na + SEG, min(SEG, N - na - SEG));
+            const int hi = na / WH;
+            if (hi != hcur || sg != tcur) __syncthreads();
+            if (hi != hcur) {
+                fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
+                hcur = hi;
             }
-            build_table<R>(tab, a, na, nw);
-            __syncthreads();
+            if (sg != tcur) {
+                stg.issue(a, na, nw);
+                stg.commit(a, tab);
+                __syncthreads();
+                tcur = sg;
+            }
+            const int hb = na - hcur * WH;   // histogram row of the segment's first step
             R ys[SEG], cs[SEG];
             R yy = CK[(size_t)sg * slot_stride + slot];
 #pragma unroll
@@ -677,16 +789,14 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
                         const R c = cs[k];
                         const R gb = lam * c;
                         lam = fma(lam * c, dsd[r], lam);
-                        scatter<R>(a, Hl, g64, k, n, L[r], gb, sc, qm);
+                        scatter<R>(a, Hl, g64, hb + k, n, L[r], gb, sc, qm);
                         y_next = ys[k];
                     }
                 }
             }
         }
         __syncthreads();
-        fold1<R>(a, H, Fb, min(SEG, N), inv_sc);
-        __syncthreads();
-        fold2(a, Fb, g64, 0, min(SEG, N));
+        fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
         const double l0 = wave_sum(active ? (double)lam : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
@@ -774,12 +884,6 @@ __global__ void k_merge2(const double *seg, int S, int Q, int n_opt, int G,
     }
 }
 
-__global__ void k_zero(double *p, size_t n) {
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
-         e += (size_t)gridDim.x * blockDim.x)
-        p[e] = 0.0;
-}
-
 // --------------------------------------------------------------------------
 // Test-support kernels
 // --------------------------------------------------------------------------
@@ -822,7 +926,7 @@ __global__ void k_debug_normals(unsigned long long seed, unsigned long long p0, 
 template <typename R>
 static size_t lds_of(int variant, const Args &a, int block, int W) {
     const int rb = sizeof(R);
-    return lds_layout(variant, rb, rb, a.I, a.J, a.n_opt, block / 64, W, a.K).total;
+    return lds_layout(variant, rb, rb, a.I, a.J, a.n_opt, block / 64, W, a.WH, a.K).total;
 }
 
 // Blocks above 64 KiB of LDS (gfx950 has 160 KiB per CU) must be allowed per kernel.
@@ -897,10 +1001,13 @@ hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block
     return hipGetLastError();
 }
 
-hipError_t launch_zero(double *p, size_t n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, p, n);
+hipError_t launch_table(const Args &a, int precision, hipStream_t st) {
+    const long long ne = (long long)a.N * a.I;
+    const int blocks = (int)((ne + 255) / 256 < 2048 ? (ne + 255) / 256 : 2048);
+    if (precision == 64)
+        hipLaunchKernelGGL(k_table<double>, dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_table<float>, dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
