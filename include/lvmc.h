@@ -102,10 +102,12 @@ typedef struct {
                                from the Philox counters); LV_ADJ_DEFAULT = LV_ADJ_STORED */
     int32_t ckpt_every;     /* checkpoint segment length: 8, 16 or 32 steps; default 16 */
     int32_t use_graph;      /* 1: capture the launch sequence in a hipGraph per shape and replay it */
-    int32_t block;          /* threads per block, a multiple of 64 in [64, 1024]; 0 = tuned default */
+    int32_t block;          /* threads per block of the adjoint (or fused) kernel, a multiple of 64 in
+                               [64, 1024] (FP32) or [64, 512] (FP64, else LV_ERR_UNSUPPORTED);
+                               0 = tuned default */
     int32_t blocks_per_cu;  /* persistent blocks per compute unit; 0 = tuned default */
     int32_t copies;         /* privatised copies of the LDS gradient histogram (1..16); 0 = default */
-    int32_t window;         /* steps per LDS vol-table window (multiple of 4 in [4, 64]); the gradient
+    int32_t window;         /* steps per LDS vol-table window (multiple of 8 in [8, 64]); the gradient
                                histogram spans the largest multiple of it that the LDS budget of
                                blocks_per_cu blocks allows (up to the whole horizon); 0 = default */
     int32_t profile;        /* 1: time every kernel with hipEvents (eager launches only), read back

@@ -170,7 +170,8 @@ int hist_window(const Plan &pl, const Shape &sh, size_t max_lds) {
 // smaller blocks for smaller problems so that every CU gets work.
 Shape default_shape(const Plan &pl, int n_cu) {
     Shape sh;
-    sh.block = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(pl.P / n_cu)));
+    const int bmax = lvk::adjoint_max_block(pl.precision == 64 ? 8 : 4);
+    sh.block = (int)std::min<long long>(bmax, std::max<long long>(64, floor_pow2(pl.P / n_cu)));
     sh.K = 2;
     sh.W = 32;
     sh.bpc = 1;
@@ -185,11 +186,15 @@ Shape default_shape(const Plan &pl, int n_cu) {
 lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds, bool may_shrink_k,
                       bool may_shrink_w) {
     const bool ckpt = pl.adjoint == LV_ADJ_CHECKPOINT;
-    while (!shape_fits(pl, sh, max_lds) && sh.W > 4 && may_shrink_w && !ckpt) sh.W /= 2;
+    while (!shape_fits(pl, sh, max_lds) && sh.W > 8 && may_shrink_w && !ckpt) sh.W /= 2;
     while (!shape_fits(pl, sh, max_lds) && sh.K > 1 && may_shrink_k) sh.K /= 2;
     if (!shape_fits(pl, sh, max_lds))
         return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)",
                     std::max(lds_adj(pl, sh, table_window(pl, sh)), lds_fwd(pl, sh)), max_lds);
+    const int bmax = lvk::adjoint_max_block(pl.precision == 64 ? 8 : 4);
+    if (sh.block > bmax)
+        return fail(ctx, LV_ERR_UNSUPPORTED, "the FP%d adjoint kernels run at most %d threads per block (asked %d)",
+                    pl.precision, bmax, sh.block);
     pl.block = sh.block;
     pl.K = sh.K;
     pl.W = table_window(pl, sh);
@@ -229,7 +234,8 @@ std::vector<Shape> forward_candidates(const Plan &pl, const Shape &base, int n_c
 
 std::vector<Shape> adjoint_candidates(const Plan &pl, const Shape &base, int n_cu, size_t max_lds) {
     std::vector<Shape> out;
-    const int bmax = (int)std::min<long long>(1024, std::max<long long>(64, floor_pow2(2 * pl.P / n_cu)));
+    const int bmax = (int)std::min<long long>(lvk::adjoint_max_block(pl.precision == 64 ? 8 : 4),
+                                              std::max<long long>(64, floor_pow2(2 * pl.P / n_cu)));
     for (int b : {128, 256, 512, 1024}) {
         if (b > bmax && b != 128) continue;
         for (int k : {1, 2, 4})
@@ -293,7 +299,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
         return fail(ctx, LV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return fail(ctx, LV_ERR_ARG, "blocks_per_cu must be in [0, 64]");
     if (o.copies < 0 || o.copies > 16) return fail(ctx, LV_ERR_ARG, "copies must be in [0, 16]");
-    if (o.window < 0 || o.window % 4 != 0 || o.window > 64) return fail(ctx, LV_ERR_ARG, "window must be a multiple of 4 in [4, 64]");
+    if (o.window < 0 || o.window % 8 != 0 || o.window > 64) return fail(ctx, LV_ERR_ARG, "window must be a multiple of 8 in [8, 64]");
 
     double tmax = 0.0;
     for (int k = 0; k < book->n_opt; ++k) {

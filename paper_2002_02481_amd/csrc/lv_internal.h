@@ -49,6 +49,10 @@ struct Args {
 
 enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };
 
+// Largest block the adjoint kernels (stored reverse, fused checkpoint) are built
+// for: 512 lanes for FP64, whose registers then fit without spills, 1024 for FP32.
+constexpr int adjoint_max_block(int real_bytes) { return real_bytes == 8 ? 512 : 1024; }
+
 // LDS bytes a kernel variant needs for the given shape (W table steps, WH
 // histogram steps).
 size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K);

@@ -124,6 +124,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Load of read-only table data at a wave-uniform address through the constant
+// address space, so that it is a scalar-cache load: it then does not share the
+// vector-memory counter that the state prefetches are waited on with.
+template <typename T>
+__device__ __forceinline__ T ldu(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // --------------------------------------------------------------------------
 // LDS carve-up, shared by the kernels and the host planner.
 // --------------------------------------------------------------------------
@@ -287,11 +295,11 @@ template <typename R>
 __device__ __forceinline__ void fwd_payoffs(const Args &a, int tap, R y, bool active, double *wpart,
                                             int wave, int lane) {
     const double S = (double)((R)a.spot * Math<R>::ex(y));
-    const int k0 = a.tap_first[tap], kc = a.tap_count[tap];
+    const int k0 = ldu(a.tap_first + tap), kc = ldu(a.tap_count + tap);
     for (int q = 0; q < kc; ++q) {
         const int k = k0 + q;
-        const double K = a.opt_strike[k];
-        double pay = a.opt_put[k] ? fmax(K - S, 0.0) : fmax(S - K, 0.0);
+        const double K = ldu(a.opt_strike + k);
+        double pay = ldu(a.opt_put + k) ? fmax(K - S, 0.0) : fmax(S - K, 0.0);
         if (!active) pay = 0.0;
         const double s1 = wave_sum(pay), s2 = wave_sum(pay * pay);
         if (lane == 0) {
@@ -306,12 +314,12 @@ template <typename R>
 __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam) {
     const R S = (R)a.spot * Math<R>::ex(y);
     const double Sd = (double)S;
-    const int k0 = a.tap_first[tap], kc = a.tap_count[tap];
+    const int k0 = ldu(a.tap_first + tap), kc = ldu(a.tap_count + tap);
     for (int q = 0; q < kc; ++q) {
         const int k = k0 + q;
-        const double K = a.opt_strike[k];
-        const R w = (R)a.cot[a.opt_orig[k]];
-        if (a.opt_put[k]) {
+        const double K = ldu(a.opt_strike + k);
+        const R w = (R)ldu(a.cot + ldu(a.opt_orig + k));
+        if (ldu(a.opt_put + k)) {
             if (Sd < K) lam -= w * S;
         } else {
             if (Sd > K) lam += w * S;
@@ -330,7 +338,7 @@ __device__ void fold(const Args &a, typename Math<R>::Acc *H, double *g64, int h
                      double inv_sc) {
     typedef typename Math<R>::Acc Acc;
     const int I = a.I, J = a.J, K = a.K, h1 = h0 + nh;
-    const int c0 = a.tj[h0], c1 = a.tj[h1 - 1];
+    const int c0 = ldu(a.tj + h0), c1 = ldu(a.tj + h1 - 1);
     const int nn = (c1 - c0 + 2) * I;   // nodes j = c0 .. c1 + 1
     for (int e = threadIdx.x; e < nn; e += blockDim.x) {
         const int jj = e / I, i = e - jj * I, j = c0 + jj;
@@ -380,8 +388,8 @@ __device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl
     } else {
         // rare: outside the fixed-point range (or not finite): FP64 LDS atomics
         // straight into the block's grid (no fold runs while steps scatter)
-        const int j = a.tj[n];
-        const double al = a.ta[n], g = (double)gb, f = (double)L.f;
+        const int j = ldu(a.tj + n);
+        const double al = ldu(a.ta + n), g = (double)gb, f = (double)L.f;
         const int J = a.J;
         atomicAdd(&g64[L.i * J + j], g * (1.0 - f) * (1.0 - al));
         atomicAdd(&g64[(L.i + 1) * J + j], g * f * (1.0 - al));
@@ -430,7 +438,7 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
         const bool active = p < a.P;
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         R y = 0;
-        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
+        int tap = 0, next_tap = a.n_taps > 0 ? ldu(a.tap_step) : -1;
         for (int wi = 0; wi < nW; ++wi) {
             const int ws = wi * W, we = min(N, ws + W);
             bool pending = false;
@@ -462,7 +470,7 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
                         if (n + 1 == next_tap) {
                             fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
                             ++tap;
-                            next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                            next_tap = tap < a.n_taps ? ldu(a.tap_step + tap) : -1;
                         }
                     }
                 }
@@ -490,8 +498,11 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
 // windows run last to first; the histogram is folded at histogram-window
 // boundaries and at the end of every tile.
 // --------------------------------------------------------------------------
+// Steps per state block of the reverse sweep (the table window is a multiple of it).
+constexpr int RB = 8;
+
 template <typename R, int AXIS>
-__global__ void __launch_bounds__(1024) k_rev(Args a) {
+__global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -515,6 +526,7 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
     Acc *Hl = H + tid % K;               // this lane's copy column
     const R *Y = (const R *)a.states;
     const size_t P = (size_t)a.P;
+    const int btop = (N - 1) / RB;   // the first (top) block of steps the sweep runs
     TabStage<R> stg;
     int wcur = -1;
     if ((int)blockIdx.x < a.n_tiles) {   // last window, into the buffer entered first
@@ -529,18 +541,21 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
         const size_t pc = active ? (size_t)p : P - 1;     // inactive lanes read a valid path
         R lam = 0;
         R y_next = Y[(size_t)(N - 1) * P + pc];
-        int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+        int tap = a.n_taps - 1, cur_tap = tap >= 0 ? ldu(a.tap_step + tap) : -1;
         int hcur = (N - 1) / WH;
-        // cur[r] = y_{4g+r} (plane 4g+r-1; y_0 = 0)
-        R cur[4], nxt[4];
-        {
-            const int g = n_groups - 1;
+        // States by blocks of RB steps (RB/4 groups of four): cur[k] = y_{b RB + k}
+        // (plane b RB + k - 1; y_0 = 0 is set where it is used).  The next block's
+        // states are loaded at the start of a block, so loads have a whole block
+        // of compute to arrive.
+        R cur[RB], nxt[RB];
+        auto load_block = [&](int b, R(&y)[RB]) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = 4 * g + r;
-                cur[r] = (n >= 1 && n <= N - 1) ? Y[(size_t)(n - 1) * P + pc] : (R)0;
+            for (int k = 0; k < RB; ++k) {
+                const int pl = min(max(b * RB + k - 1, 0), N - 1);
+                y[k] = Y[(size_t)pl * P + pc];
             }
-        }
+        };
+        load_block(btop, cur);
         for (int wi = nW - 1; wi >= 0; --wi) {
             const int ws = wi * W, we = min(N, ws + W);
             bool pending = false;
@@ -562,62 +577,57 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
                 }
             }
             const int hbase = hcur * WH;
-            for (int g = (we - 1) >> 2; g >= (ws >> 2); --g) {
-                const int n0 = g << 2;
-                if (g > 0) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int n = 4 * (g - 1) + r;
-                        nxt[r] = n >= 1 ? Y[(size_t)(n - 1) * P + pc] : (R)0;
-                    }
-                }
+            // one group of four steps n0 .. n0+3 whose states are y[0..3]
+            auto group = [&](int n0, const R *y, auto full_tag) {
+                constexpr bool FULL = decltype(full_tag)::value;
                 const int wn0 = n0 - ws, hn0 = n0 - hbase;
-                auto group = [&](auto full_tag) {
-                    constexpr bool FULL = decltype(full_tag)::value;
-                    Look<R> L[4];
-                    R cc[4], dsd[4], yup[4];
+                Look<R> L[4];
+                R cc[4], dsd[4], yup[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (FULL || n0 + r < N) {
-                            yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : cur[r + 1];
-                            L[r] = lookup<R, AXIS>(cur[r], tuse + 2 * (wn0 + r) * I, inv_du, a_off,
-                                                   amax, imax, spot);
-                            cc[r] = (yup[r] - cur[r]) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
-                            R d = L[r].in ? L[r].d * inv_du : (R)0;
-                            if (AXIS == 0) d *= L[r].S;
-                            dsd[r] = d;
-                        }
+                for (int r = 0; r < 4; ++r) {
+                    if (FULL || n0 + r < N) {
+                        const R yr = (n0 + r == 0) ? (R)0 : y[r];
+                        yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : y[r + 1];
+                        L[r] = lookup<R, AXIS>(yr, tuse + 2 * (wn0 + r) * I, inv_du, a_off, amax,
+                                               imax, spot);
+                        cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
+                        R d = L[r].in ? L[r].d * inv_du : (R)0;
+                        if (AXIS == 0) d *= L[r].S;
+                        dsd[r] = d;
                     }
+                }
 #pragma unroll
-                    for (int r = 3; r >= 0; --r) {
-                        const int n = n0 + r;
-                        if (FULL || n < N) {
-                            if (n + 1 == cur_tap) {
-                                lam = rev_seeds<R>(a, tap, yup[r], lam);
-                                if (!active) lam = 0;
-                                --tap;
-                                cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
-                            }
-                            const R gb = lam * cc[r];
-                            lam = fma(lam * cc[r], dsd[r], lam);
-                            scatter<R>(a, Hl, g64, hn0 + r, n, L[r], gb, sc, qm);
+                for (int r = 3; r >= 0; --r) {
+                    const int n = n0 + r;
+                    if (FULL || n < N) {
+                        if (n + 1 == cur_tap) {
+                            lam = rev_seeds<R>(a, tap, yup[r], lam);
+                            if (!active) lam = 0;
+                            --tap;
+                            cur_tap = tap >= 0 ? ldu(a.tap_step + tap) : -1;
                         }
+                        const R gb = lam * cc[r];
+                        lam = fma(lam * cc[r], dsd[r], lam);
+                        scatter<R>(a, Hl, g64, hn0 + r, n, L[r], gb, sc, qm);
                     }
-                };
-                if (n0 + 4 <= N)
-                    group(std::true_type{});
-                else
-                    group(std::false_type{});
-                y_next = cur[0];
-                if (g > 0) {
+                }
+                if (FULL || n0 < N) y_next = (n0 == 0) ? (R)0 : y[0];
+            };
+            auto block = [&](int b, auto full_tag) {
+                load_block(max(b - 1, 0), nxt);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) cur[r] = nxt[r];
-                }
-                if (pending) {
-                    stg.commit(a, tnext);
-                    pending = false;
-                }
-            }
+                for (int q = RB / 4 - 1; q >= 0; --q) group(b * RB + 4 * q, cur + 4 * q, full_tag);
+#pragma unroll
+                for (int k = 0; k < RB; ++k) cur[k] = nxt[k];
+            };
+            // The window's first block runs on its own (the horizon's top block may
+            // be partial), then the next table window is committed, then the rest.
+            const int blo = ws / RB;
+            int b = (we - 1) / RB;
+            if (wi == nW - 1) block(b, std::false_type{});
+            else block(b, std::true_type{});
+            if (pending) stg.commit(a, tnext);
+            for (--b; b >= blo; --b) block(b, std::true_type{});
         }
         __syncthreads();
         fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
@@ -646,7 +656,7 @@ __global__ void __launch_bounds__(1024) k_rev(Args a) {
 // tile) share its copy.
 // --------------------------------------------------------------------------
 template <typename R, int AXIS, int SEG>
-__global__ void __launch_bounds__(1024) k_fused(Args a) {
+__global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -682,7 +692,7 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         // ---- forward: checkpoints and payoff sums
         R y = 0;
-        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
+        int tap = 0, next_tap = a.n_taps > 0 ? ldu(a.tap_step) : -1;
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
             CK[(size_t)sg * slot_stride + slot] = y;
@@ -711,7 +721,7 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
                             if (n + 1 == next_tap) {
                                 fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
                                 ++tap;
-                                next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                                next_tap = tap < a.n_taps ? ldu(a.tap_step + tap) : -1;
                             }
                         }
                     }
@@ -720,7 +730,7 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
         }
         // ---- reverse, segment by segment
         R lam = 0, y_next = y;
-        int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+        int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? ldu(a.tap_step + rtap) : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
@@ -784,7 +794,7 @@ __global__ void __launch_bounds__(1024) k_fused(Args a) {
                             lam = rev_seeds<R>(a, rtap, y_next, lam);
                             if (!active) lam = 0;
                             --rtap;
-                            cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+                            cur_tap = rtap >= 0 ? ldu(a.tap_step + rtap) : -1;
                         }
                         const R c = cs[k];
                         const R gb = lam * c;

@@ -51,6 +51,9 @@ def test_check_accepts_valid_requests():
     (dict(ckpt_every=12), _lib.LV_ERR_ARG),
     (dict(block=100), _lib.LV_ERR_ARG),
     (dict(copies=17), _lib.LV_ERR_ARG),
+    (dict(window=4), _lib.LV_ERR_ARG),
+    (dict(window=12), _lib.LV_ERR_ARG),
+    (dict(precision=64, block=1024), _lib.LV_ERR_UNSUPPORTED),
     (dict(strikes=np.full(300, 100.0), maturities=np.full(300, 1.0)), _lib.LV_ERR_UNSUPPORTED),
 ])
 def test_check_rejects(kw, status):

@@ -188,7 +188,7 @@ def test_block_shapes_agree(lv, ctx, orc):
     wl = W.small_call()
     ref = orc.price_and_grad(wl.surface.rounded_to_f32(), wl.book, wl.n_paths, wl.n_steps)
     for opts in [dict(block=64), dict(block=128, copies=1), dict(block=512, copies=16),
-                 dict(block=256, window=4), dict(block=256, window=32, blocks_per_cu=1),
+                 dict(block=256, window=8), dict(block=256, window=32, blocks_per_cu=1),
                  dict(block=1024, copies=4), dict(adjoint="checkpoint", ckpt_every=8),
                  dict(adjoint="checkpoint", ckpt_every=32, block=128)]:
         got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, 0, **opts)
@@ -332,6 +332,12 @@ def test_full_size_single_call_60x30(lv, ctx, orc):
         assert np.all((e <= GRAD_TOL * scale) | (e <= 0.25 * se * math.sqrt(wl.n_paths * n_b))), f"block {b}"
     got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed, precision=64)
     blocks = ctx.block_grads(wl.surface.sigma.size)
+    # the FP64 kernels run a launch shape of their own (at most 512 lanes per block)
+    info = ctx.run_info()
+    B, T = info["n_blocks"], info["tile_paths"]
+    n_tiles = (wl.n_paths + T - 1) // T
+    sampled = (0, 1, B // 2, B - 1)
+    ranges = {b: [(t * T, min((t + 1) * T, wl.n_paths)) for t in range(b, n_tiles, B)] for b in sampled}
     for b in sampled:
         r = orc.sums(wl.surface, wl.book, wl.n_steps, wl.seed, ranges[b])
         gb = blocks[b].reshape(wl.surface.sigma.shape)
