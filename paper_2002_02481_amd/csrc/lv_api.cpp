@@ -159,7 +159,7 @@ int hist_window(const Plan &pl, const Shape &sh, size_t max_lds) {
     const int resident = std::max(1, std::min(sh.bpc, 2048 / sh.block));
     const size_t budget = max_lds / resident;
     const size_t base = lds_adj(pl, sh, 0);
-    const size_t per_step = (size_t)pl.I * sh.K * (pl.precision == 64 ? 8 : 4);
+    const size_t per_step = (size_t)(pl.I + 1) * sh.K * (pl.precision == 64 ? 8 : 4);
     long long wh = budget > base ? (long long)((budget - base) / per_step) / W * W : 0;
     wh = std::max<long long>(W, std::min(wh, whole));
     return (int)wh;

@@ -88,7 +88,21 @@ struct Math<float> {
         return __builtin_amdgcn_exp2f(y * 1.44269504f);
     }
     __device__ static __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    __device__ static __forceinline__ Acc to_acc(float x) { return __float2int_rn(x); }
+    // (q0, q1) = (rn(x) - rn(xf), rn(xf)).  For |x|, |xf| <= 2^22 (MAGIC_MAX) adding
+    // 1.5 * 2^23 rounds to an integer (nearest, ties to even) held in the low
+    // mantissa bits, so bit patterns differ by the integers themselves; larger
+    // ranges (blocks with few paths) convert with round-to-nearest.
+    static constexpr double MAGIC_MAX = 4194304.0;
+    __device__ static __forceinline__ void to_acc2(float x, float xf, bool magic, Acc &q0, Acc &q1) {
+        if (magic) {
+            const int bx = __float_as_int(x + 12582912.0f), bf = __float_as_int(xf + 12582912.0f);
+            q0 = bx - bf;
+            q1 = bf - 0x4B400000;
+        } else {
+            q1 = __float2int_rn(xf);
+            q0 = __float2int_rn(x) - q1;
+        }
+    }
     __device__ static __forceinline__ void acc_add(Acc *p, Acc v) { atomicAdd(p, v); }
 };
 
@@ -110,7 +124,14 @@ struct Math<double> {
     }
     __device__ static __forceinline__ double ex(double y) { return exp(y); }
     __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
-    __device__ static __forceinline__ Acc to_acc(double x) { return __double2ll_rn(x); }
+    // as for float with 1.5 * 2^52; the FP64 range is capped at 2^51, so always exact
+    static constexpr double MAGIC_MAX = 2251799813685248.0;
+    __device__ static __forceinline__ void to_acc2(double x, double xf, bool, Acc &q0, Acc &q1) {
+        const long long bx = __double_as_longlong(x + 6755399441055744.0);
+        const long long bf = __double_as_longlong(xf + 6755399441055744.0);
+        q0 = bx - bf;
+        q1 = bf - 0x4338000000000000LL;
+    }
     __device__ static __forceinline__ void acc_add(Acc *p, Acc v) {
         atomicAdd((unsigned long long *)p, (unsigned long long)v);
     }
@@ -126,7 +147,9 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 
 // Load of read-only table data at a wave-uniform address through the constant
 // address space, so that it is a scalar-cache load: it then does not share the
-// vector-memory counter that the state prefetches are waited on with.
+// vector-memory counter that the state prefetches are waited on with.  Scalar loads
+// return out of order, so waiting for one waits for every LDS operation as well: a
+// value that stays live across steps (the next tap step) is read with a vector load.
 template <typename T>
 __device__ __forceinline__ T ldu(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
@@ -155,7 +178,7 @@ __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes,
     L.tab = off;
     off += align16((size_t)tab_bufs * W * I * 2 * rbytes);
     L.hist = off;
-    off += grad ? align16((size_t)WH * I * K * accbytes) : 0;
+    off += grad ? align16((size_t)WH * K * (I + 1) * accbytes) : 0;   // rows of I + 1 words
     L.total = off;
     return L;
 }
@@ -170,8 +193,9 @@ __host__ __device__ double fixed_point_qmax(int precision, int block, int K, lon
     // at most one term per path of its copy class between folds (one tile) and must
     // stay inside int32.  FP64: the K words of a node are summed in int64 at the
     // fold, so all of a tile's terms must fit.
+    // FP64 is capped at 2^51, where the rounding of terms to integers stays exact.
     const int act = (int)(P < block ? P : block);
-    if (precision == 64) return ldexp(1.0, 62) / act;
+    if (precision == 64) return fmin(ldexp(1.0, 62) / act, ldexp(1.0, 51));
     return floor(2147483000.0 / (double)((act + K - 1) / K)) - 2.0;
 }
 
@@ -267,8 +291,7 @@ struct Look {
 };
 
 template <typename R, int AXIS>
-__device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off, R amax, int imax,
-                                          R spot) {
+__device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off, R amax, R spot) {
     Look<R> L;
     R x;
     if (AXIS == 0) {
@@ -281,7 +304,9 @@ __device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off,
     const R a = fma(x, inv_du, a_off);
     L.in = (a > (R)0) && (a < amax);
     const R ac = clamp_to(a, amax);
-    L.i = min((int)ac, imax);
+    // i = I - 1 only at (or beyond) the top node: there f = 0 and the table's d = 0,
+    // so the value is the node's and the term for node i + 1 is zero
+    L.i = (int)ac;
     L.f = ac - (R)L.i;
     const R c = trow[2 * L.i], d = trow[2 * L.i + 1];
     L.s = fma(L.f, d, c);
@@ -309,16 +334,17 @@ __device__ __forceinline__ void fwd_payoffs(const Args &a, int tap, R y, bool ac
     }
 }
 
-// Adjoint seeds at step n+1: lambda += sum_k w_k d payoff_k / d y.
+// Adjoint seeds at step n+1: lambda += scale sum_k w_k d payoff_k / d y (the
+// adjoint kernels carry lambda scaled by the fixed-point scale 2^F).
 template <typename R>
-__device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam) {
+__device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam, double scale) {
     const R S = (R)a.spot * Math<R>::ex(y);
     const double Sd = (double)S;
     const int k0 = ldu(a.tap_first + tap), kc = ldu(a.tap_count + tap);
     for (int q = 0; q < kc; ++q) {
         const int k = k0 + q;
         const double K = ldu(a.opt_strike + k);
-        const R w = (R)ldu(a.cot + ldu(a.opt_orig + k));
+        const R w = (R)(ldu(a.cot + ldu(a.opt_orig + k)) * scale);
         if (ldu(a.opt_put + k)) {
             if (Sd < K) lam -= w * S;
         } else {
@@ -329,6 +355,7 @@ __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam) {
 }
 
 // Fold of the histogram rows of steps [h0, h0 + nh) into the block's FP64 grid.
+// The histogram is H[n][copy][I + 1] (the last word of a row only ever receives 0).
 // Node (i, j) takes alpha_n of every row n of time cell j - 1 and 1 - alpha_n of
 // every row of cell j (the steps of a cell are contiguous), so each node has one
 // owner thread and no atomics are needed; the rows are then cleared.  Callers
@@ -346,55 +373,55 @@ __device__ void fold(const Args &a, typename Math<R>::Acc *H, double *g64, int h
         if (j > c0) {
             const int lo = max(a.cell_lo[j - 1], h0), hi = min(a.cell_lo[j], h1);
             for (int n = lo; n < hi; ++n) {
-                const Acc *h = H + ((size_t)(n - h0) * I + i) * K;
+                const Acc *h = H + (size_t)(n - h0) * K * (I + 1) + i;
                 long long q = 0;
-                for (int c = 0; c < K; ++c) q += (long long)h[c];
+                for (int c = 0; c < K; ++c) q += (long long)h[c * (I + 1)];
                 acc += a.ta[n] * ((double)q * inv_sc);
             }
         }
         if (j <= c1) {
             const int lo = max(a.cell_lo[j], h0), hi = min(a.cell_lo[j + 1], h1);
             for (int n = lo; n < hi; ++n) {
-                const Acc *h = H + ((size_t)(n - h0) * I + i) * K;
+                const Acc *h = H + (size_t)(n - h0) * K * (I + 1) + i;
                 long long q = 0;
-                for (int c = 0; c < K; ++c) q += (long long)h[c];
+                for (int c = 0; c < K; ++c) q += (long long)h[c * (I + 1)];
                 acc += (1.0 - a.ta[n]) * ((double)q * inv_sc);
             }
         }
         g64[i * J + j] += acc;
     }
     __syncthreads();
-    const size_t words = (size_t)nh * I * K, n16 = words * sizeof(Acc) / 16;
+    const size_t words = (size_t)nh * K * (I + 1), n16 = words * sizeof(Acc) / 16;
     int4 *h4 = (int4 *)H;
     for (size_t e = threadIdx.x; e < n16; e += blockDim.x) h4[e] = make_int4(0, 0, 0, 0);
     for (size_t e = n16 * 16 / sizeof(Acc) + threadIdx.x; e < words; e += blockDim.x) H[e] = 0;
     __syncthreads();
 }
 
-// Scatter of one step's adjoint term x = gb * 2^F: x(1-f) to node i and x f to
-// node i+1 of histogram row wn, in this lane's copy column Hl (= H + lane copy).
+// Scatter of one step's adjoint term x (lambda c, already scaled by 2^F): x(1-f)
+// to node i and x f to node i+1 of this lane's histogram row hrow.
 template <typename R>
-__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *Hl, double *g64, int wn,
-                                        int n, const Look<R> &L, R gb, R sc, R qm) {
+__device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *hrow, double *g64, int n,
+                                        const Look<R> &L, R x, R qm, bool magic, double inv_sc) {
     typedef typename Math<R>::Acc Acc;
-    const R x = gb * sc;
-    if (x == (R)0) return;
+    if (x == (R)0) return;   // lanes whose adjoint is zero (paths out of the money) stay idle
     if (fabs(x) <= qm) {
-        const Acc q1 = Math<R>::to_acc(x * L.f);
-        const Acc q0 = Math<R>::to_acc(x) - q1;
-        Acc *h = Hl + __umul24((unsigned)(wn * a.I + L.i), (unsigned)a.K);
+        Acc q0, q1;
+        Math<R>::to_acc2(x, x * L.f, magic, q0, q1);
+        Acc *h = hrow + L.i;
         Math<R>::acc_add(h, q0);
-        Math<R>::acc_add(h + a.K, q1);
+        Math<R>::acc_add(h + 1, q1);
     } else {
         // rare: outside the fixed-point range (or not finite): FP64 LDS atomics
         // straight into the block's grid (no fold runs while steps scatter)
-        const int j = ldu(a.tj + n);
-        const double al = ldu(a.ta + n), g = (double)gb, f = (double)L.f;
-        const int J = a.J;
-        atomicAdd(&g64[L.i * J + j], g * (1.0 - f) * (1.0 - al));
-        atomicAdd(&g64[(L.i + 1) * J + j], g * f * (1.0 - al));
-        atomicAdd(&g64[L.i * J + j + 1], g * (1.0 - f) * al);
-        atomicAdd(&g64[(L.i + 1) * J + j + 1], g * f * al);
+        const int i = min(L.i, a.I - 2);
+        const double f = (double)L.f + (double)(L.i - i);   // 1 at the top node
+        const int j = ldu(a.tj + n), J = a.J;
+        const double al = ldu(a.ta + n), g = (double)x * inv_sc;
+        atomicAdd(&g64[i * J + j], g * (1.0 - f) * (1.0 - al));
+        atomicAdd(&g64[(i + 1) * J + j], g * f * (1.0 - al));
+        atomicAdd(&g64[i * J + j + 1], g * (1.0 - f) * al);
+        atomicAdd(&g64[(i + 1) * J + j + 1], g * f * al);
     }
 }
 
@@ -424,7 +451,6 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
 
     const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
     const R spot = (R)a.spot, amax = (R)(I - 1);
-    const int imax = I - 2;
     TabStage<R> stg;
     int wcur = -1;
     if ((int)blockIdx.x < a.n_tiles) {   // first window, into the buffer entered first
@@ -438,7 +464,7 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
         const bool active = p < a.P;
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         R y = 0;
-        int tap = 0, next_tap = a.n_taps > 0 ? ldu(a.tap_step) : -1;
+        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int wi = 0; wi < nW; ++wi) {
             const int ws = wi * W, we = min(N, ws + W);
             bool pending = false;
@@ -464,13 +490,13 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
                     const int n = n0 + r;
                     if (n < N) {
                         const R *trow = tuse + 2 * (n - ws) * I;
-                        const Look<R> L = lookup<R, AXIS>(y, trow, inv_du, a_off, amax, imax, spot);
+                        const Look<R> L = lookup<R, AXIS>(y, trow, inv_du, a_off, amax, spot);
                         y = fma(L.s, fma(-hdt, L.s, z[r]), y);
                         if (STORE && active) ((R *)a.states)[(size_t)n * a.P + p] = y;
                         if (n + 1 == next_tap) {
                             fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
                             ++tap;
-                            next_tap = tap < a.n_taps ? ldu(a.tap_step + tap) : -1;
+                            next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
                         }
                     }
                 }
@@ -501,7 +527,7 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
 // Steps per state block of the reverse sweep (the table window is a multiple of it).
 constexpr int RB = 8;
 
-template <typename R, int AXIS>
+template <typename R, int AXIS, bool MAGIC>
 __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -514,16 +540,17 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     Acc *H = (Acc *)(smem + lay.hist);
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
-    for (int e = tid; e < WH * I * a.K; e += blockDim.x) H[e] = 0;
+    for (int e = tid; e < WH * a.K * (I + 1); e += blockDim.x) H[e] = 0;
 
     const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K, a.P);
     const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
-    const R sc = (R)ldexp(1.0, F), qm = (R)qmax;
-    const double inv_sc = ldexp(1.0, -F);
+    const R qm = (R)qmax;
+    constexpr bool magic = MAGIC;   // the launcher chose it: qmax <= Math<R>::MAGIC_MAX
+    const double scd = ldexp(1.0, F), inv_sc = ldexp(1.0, -F);
     const R hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
     const R spot = (R)a.spot, amax = (R)(I - 1);
-    const int imax = I - 2, n_groups = (N + 3) >> 2, K = a.K;
-    Acc *Hl = H + tid % K;               // this lane's copy column
+    const int n_groups = (N + 3) >> 2, K = a.K, KI1 = K * (I + 1);
+    Acc *Hl = H + (tid % K) * (I + 1);   // this lane's copy of a histogram row
     const R *Y = (const R *)a.states;
     const size_t P = (size_t)a.P;
     const int btop = (N - 1) / RB;   // the first (top) block of steps the sweep runs
@@ -539,9 +566,9 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
         const long long p = (long long)tile * blockDim.x + tid;
         const bool active = p < a.P;
         const size_t pc = active ? (size_t)p : P - 1;     // inactive lanes read a valid path
-        R lam = 0;
+        R lam = 0;   // the adjoint of y, times 2^F
         R y_next = Y[(size_t)(N - 1) * P + pc];
-        int tap = a.n_taps - 1, cur_tap = tap >= 0 ? ldu(a.tap_step + tap) : -1;
+        int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
         int hcur = (N - 1) / WH;
         // States by blocks of RB steps (RB/4 groups of four): cur[k] = y_{b RB + k}
         // (plane b RB + k - 1; y_0 = 0 is set where it is used).  The next block's
@@ -589,7 +616,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
                         const R yr = (n0 + r == 0) ? (R)0 : y[r];
                         yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : y[r + 1];
                         L[r] = lookup<R, AXIS>(yr, tuse + 2 * (wn0 + r) * I, inv_du, a_off, amax,
-                                               imax, spot);
+                                               spot);
                         cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
                         R d = L[r].in ? L[r].d * inv_du : (R)0;
                         if (AXIS == 0) d *= L[r].S;
@@ -601,14 +628,14 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
                     const int n = n0 + r;
                     if (FULL || n < N) {
                         if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R>(a, tap, yup[r], lam);
+                            lam = rev_seeds<R>(a, tap, yup[r], lam, scd);
                             if (!active) lam = 0;
                             --tap;
-                            cur_tap = tap >= 0 ? ldu(a.tap_step + tap) : -1;
+                            cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
                         }
-                        const R gb = lam * cc[r];
-                        lam = fma(lam * cc[r], dsd[r], lam);
-                        scatter<R>(a, Hl, g64, hn0 + r, n, L[r], gb, sc, qm);
+                        const R x = lam * cc[r];   // lam carries 2^F: x is the fixed-point term
+                        lam = fma(x, dsd[r], lam);
+                        scatter<R>(a, Hl + (hn0 + r) * KI1, g64, n, L[r], x, qm, magic, inv_sc);
                     }
                 }
                 if (FULL || n0 < N) y_next = (n0 == 0) ? (R)0 : y[0];
@@ -631,7 +658,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
         }
         __syncthreads();
         fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
-        const double l0 = wave_sum(active ? (double)lam : 0.0);
+        const double l0 = wave_sum(active ? (double)lam * inv_sc : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
     __syncthreads();
@@ -655,7 +682,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
 // one forward then backward, the first one backward then forward for the next
 // tile) share its copy.
 // --------------------------------------------------------------------------
-template <typename R, int AXIS, int SEG>
+template <typename R, int AXIS, int SEG, bool MAGIC>
 __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -670,16 +697,17 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
-    for (int e = tid; e < WH * I * a.K; e += blockDim.x) H[e] = 0;
+    for (int e = tid; e < WH * a.K * (I + 1); e += blockDim.x) H[e] = 0;
 
     const double qmax = fixed_point_qmax(sizeof(R) == 8 ? 64 : 32, blockDim.x, a.K, a.P);
     const int F = fixed_point_bits(a, qmax, Math<R>::FMAX);
-    const R sc = (R)ldexp(1.0, F), qm = (R)qmax;
-    const double inv_sc = ldexp(1.0, -F);
+    const R qm = (R)qmax;
+    constexpr bool magic = MAGIC;   // the launcher chose it: qmax <= Math<R>::MAGIC_MAX
+    const double scd = ldexp(1.0, F), inv_sc = ldexp(1.0, -F);
     const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
     const R spot = (R)a.spot, amax = (R)(I - 1);
-    const int imax = I - 2, n_seg = (N + SEG - 1) / SEG;
-    Acc *Hl = H + tid % a.K;
+    const int n_seg = (N + SEG - 1) / SEG, KI1 = a.K * (I + 1);
+    Acc *Hl = H + (tid % a.K) * (I + 1);   // this lane's copy of a histogram row
     R *CK = (R *)a.ckpt;
     const size_t slot_stride = (size_t)gridDim.x * blockDim.x;
     const size_t slot = (size_t)blockIdx.x * blockDim.x + tid;
@@ -692,7 +720,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         // ---- forward: checkpoints and payoff sums
         R y = 0;
-        int tap = 0, next_tap = a.n_taps > 0 ? ldu(a.tap_step) : -1;
+        int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
             CK[(size_t)sg * slot_stride + slot] = y;
@@ -716,21 +744,21 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         const int n = n0 + r;
                         if (n < N) {
                             const Look<R> L = lookup<R, AXIS>(y, tab + 2 * (4 * q4 + r) * I, inv_du,
-                                                              a_off, amax, imax, spot);
+                                                              a_off, amax, spot);
                             y = fma(L.s, fma(-hdt, L.s, z[r]), y);
                             if (n + 1 == next_tap) {
                                 fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
                                 ++tap;
-                                next_tap = tap < a.n_taps ? ldu(a.tap_step + tap) : -1;
+                                next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
                             }
                         }
                     }
                 }
             }
         }
-        // ---- reverse, segment by segment
+        // ---- reverse, segment by segment (lam is the adjoint of y times 2^F)
         R lam = 0, y_next = y;
-        int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? ldu(a.tap_step + rtap) : -1;
+        int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
@@ -762,7 +790,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         const int k = 4 * q4 + r;
                         if (n0 + r < N) {
                             const Look<R> L = lookup<R, AXIS>(yy, tab + 2 * k * I, inv_du, a_off,
-                                                              amax, imax, spot);
+                                                              amax, spot);
                             ys[k] = yy;
                             cs[k] = fma((R)-2 * hdt, L.s, z[r]);
                             yy = fma(L.s, fma(-hdt, L.s, z[r]), yy);
@@ -779,7 +807,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 for (int r = 0; r < 4; ++r) {
                     const int k = 4 * q4 + r;
                     if (na + k < N) {
-                        L[r] = lookup<R, AXIS>(ys[k], tab + 2 * k * I, inv_du, a_off, amax, imax, spot);
+                        L[r] = lookup<R, AXIS>(ys[k], tab + 2 * k * I, inv_du, a_off, amax, spot);
                         R d = L[r].in ? L[r].d * inv_du : (R)0;
                         if (AXIS == 0) d *= L[r].S;
                         dsd[r] = d;
@@ -791,15 +819,14 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     const int n = na + k;
                     if (n < N) {
                         if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R>(a, rtap, y_next, lam);
+                            lam = rev_seeds<R>(a, rtap, y_next, lam, scd);
                             if (!active) lam = 0;
                             --rtap;
-                            cur_tap = rtap >= 0 ? ldu(a.tap_step + rtap) : -1;
+                            cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
                         }
-                        const R c = cs[k];
-                        const R gb = lam * c;
-                        lam = fma(lam * c, dsd[r], lam);
-                        scatter<R>(a, Hl, g64, hb + k, n, L[r], gb, sc, qm);
+                        const R x = lam * cs[k];   // lam carries 2^F: x is the fixed-point term
+                        lam = fma(x, dsd[r], lam);
+                        scatter<R>(a, Hl + (hb + k) * KI1, g64, n, L[r], x, qm, magic, inv_sc);
                         y_next = ys[k];
                     }
                 }
@@ -807,7 +834,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         }
         __syncthreads();
         fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
-        const double l0 = wave_sum(active ? (double)lam : 0.0);
+        const double l0 = wave_sum(active ? (double)lam * inv_sc : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
     __syncthreads();
@@ -976,38 +1003,52 @@ hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int 
     return hipGetLastError();
 }
 
+// Whether the adjoint kernels may round fixed-point terms with the magic-constant
+// add (the term range fits it); FP64 ranges always do.
+static bool use_magic(const Args &a, int precision, int block) {
+    const double qmax = fixed_point_qmax(precision, block, a.K, a.P);
+    return precision == 64 || qmax <= Math<float>::MAGIC_MAX;
+}
+
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st) {
     if (precision == 64) {
         const size_t lds = lds_of<double>(REV_STORED, a, block, a.W);
-        if (a.axis == 0) LAUNCH((k_rev<double, 0>), blocks, block, lds, st, a);
-        else LAUNCH((k_rev<double, 1>), blocks, block, lds, st, a);
+        if (a.axis == 0) LAUNCH((k_rev<double, 0, true>), blocks, block, lds, st, a);
+        else LAUNCH((k_rev<double, 1, true>), blocks, block, lds, st, a);
     } else {
         const size_t lds = lds_of<float>(REV_STORED, a, block, a.W);
-        if (a.axis == 0) LAUNCH((k_rev<float, 0>), blocks, block, lds, st, a);
-        else LAUNCH((k_rev<float, 1>), blocks, block, lds, st, a);
+        const bool m = use_magic(a, precision, block);
+        if (a.axis == 0) {
+            if (m) LAUNCH((k_rev<float, 0, true>), blocks, block, lds, st, a);
+            else LAUNCH((k_rev<float, 0, false>), blocks, block, lds, st, a);
+        } else {
+            if (m) LAUNCH((k_rev<float, 1, true>), blocks, block, lds, st, a);
+            else LAUNCH((k_rev<float, 1, false>), blocks, block, lds, st, a);
+        }
     }
     return hipGetLastError();
 }
 
-template <typename R, int SEG>
+template <typename R, int SEG, bool MAGIC>
 static void fused_seg(const Args &a, int blocks, int block, hipStream_t st) {
     const size_t lds = lds_of<R>(FUSED_CKPT, a, block, SEG);
-    if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG>), blocks, block, lds, st, a);
-    else LAUNCH((k_fused<R, 1, SEG>), blocks, block, lds, st, a);
+    if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG, MAGIC>), blocks, block, lds, st, a);
+    else LAUNCH((k_fused<R, 1, SEG, MAGIC>), blocks, block, lds, st, a);
 }
 
-template <typename R>
+template <typename R, bool MAGIC>
 static void fused_any(const Args &a, int blocks, int block, hipStream_t st) {
     switch (a.seg) {
-        case 8: fused_seg<R, 8>(a, blocks, block, st); break;
-        case 16: fused_seg<R, 16>(a, blocks, block, st); break;
-        default: fused_seg<R, 32>(a, blocks, block, st); break;
+        case 8: fused_seg<R, 8, MAGIC>(a, blocks, block, st); break;
+        case 16: fused_seg<R, 16, MAGIC>(a, blocks, block, st); break;
+        default: fused_seg<R, 32, MAGIC>(a, blocks, block, st); break;
     }
 }
 
 hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st) {
-    if (precision == 64) fused_any<double>(a, blocks, block, st);
-    else fused_any<float>(a, blocks, block, st);
+    if (precision == 64) fused_any<double, true>(a, blocks, block, st);
+    else if (use_magic(a, precision, block)) fused_any<float, true>(a, blocks, block, st);
+    else fused_any<float, false>(a, blocks, block, st);
     return hipGetLastError();
 }
 
