@@ -118,6 +118,9 @@ typedef struct {
     int32_t fwd_block;      /* threads per block of the separate forward kernel (stored and
                                price-only paths); 0 = tuned default */
     int32_t fwd_blocks_per_cu; /* persistent blocks per CU of that forward kernel; 0 = default */
+    int32_t dense_adjoint;  /* stored adjoint: 1 = sweep every path back; 0 (default) = sweep only
+                               the paths with an option in the money at its maturity, since every
+                               other path has a zero adjoint and contributes exactly nothing */
 } lv_opts;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`

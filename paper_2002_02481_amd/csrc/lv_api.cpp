@@ -41,7 +41,8 @@ struct Plan {
     std::vector<int> tj, cell_lo, tap_step, tap_first, tap_count, opt_put, opt_orig;
     std::vector<double> ta, opt_strike, weight;
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;
-    int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, S = 32, bpc = 2;
+    int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, S = 32, bpc = 2, CH = 1;
+    int dense = 0;   // reverse kernel sweeps every path (not only those with a nonzero adjoint)
     int fblock = 256, fblocks = 0, f_n_tiles = 0, fbpc = 2;
     int G = 0, Q = 0;
     Shape user{0, 0, 0, 0, 0, 0};   // caller-fixed shape fields (0 = free)
@@ -135,30 +136,40 @@ int floor_pow2(long long x) {
 // fused kernel.
 int table_window(const Plan &pl, const Shape &sh) { return pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W; }
 
-size_t lds_adj(const Plan &pl, const Shape &sh, int WH) {
+// Path tiles per live-path list of the stored reverse kernel: all of a block's
+// tiles, up to 4.
+int chunk_tiles(const Plan &pl, const Shape &sh, int n_cu) {
+    if (pl.adjoint == LV_ADJ_CHECKPOINT) return 1;
+    const long long tiles = (pl.P + sh.block - 1) / sh.block;
+    const long long blocks = std::min<long long>(tiles, (long long)n_cu * sh.bpc);
+    return (int)std::max<long long>(1, std::min<long long>(4, (tiles + blocks - 1) / blocks));
+}
+
+size_t lds_adj(const Plan &pl, const Shape &sh, int WH, int n_cu) {
     const int var = pl.adjoint == LV_ADJ_CHECKPOINT ? lvk::FUSED_CKPT : lvk::REV_STORED;
-    return lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, table_window(pl, sh), WH, sh.K);
+    return lvk::lds_bytes(var, pl.precision, pl.I, pl.J, pl.n_opt, sh.block, table_window(pl, sh), WH, sh.K,
+                          chunk_tiles(pl, sh, n_cu));
 }
 
 size_t lds_fwd(const Plan &pl, const Shape &sh) {
     return lvk::lds_bytes(lvk::FWD_STORE, pl.precision, pl.I, pl.J, pl.n_opt, sh.fblock, table_window(pl, sh), 0,
-                          sh.K);
+                          sh.K, 0);
 }
 
 // Whether the shape fits the CU's LDS with the smallest histogram window.
-bool shape_fits(const Plan &pl, const Shape &sh, size_t max_lds) {
-    return lds_adj(pl, sh, table_window(pl, sh)) <= max_lds && lds_fwd(pl, sh) <= max_lds;
+bool shape_fits(const Plan &pl, const Shape &sh, size_t max_lds, int n_cu) {
+    return lds_adj(pl, sh, table_window(pl, sh), n_cu) <= max_lds && lds_fwd(pl, sh) <= max_lds;
 }
 
 // Histogram window: the largest multiple of the table window (up to the whole
 // horizon) whose block still leaves room for the blocks per CU the shape asks
 // for (at most 2048 lanes per CU).  Fewer windows mean fewer folds.
-int hist_window(const Plan &pl, const Shape &sh, size_t max_lds) {
+int hist_window(const Plan &pl, const Shape &sh, size_t max_lds, int n_cu) {
     const int W = table_window(pl, sh);
     const long long whole = ((long long)pl.N + W - 1) / W * W;
     const int resident = std::max(1, std::min(sh.bpc, 2048 / sh.block));
     const size_t budget = max_lds / resident;
-    const size_t base = lds_adj(pl, sh, 0);
+    const size_t base = lds_adj(pl, sh, 0, n_cu);
     const size_t per_step = (size_t)(pl.I + 1) * sh.K * (pl.precision == 64 ? 8 : 4);
     long long wh = budget > base ? (long long)((budget - base) / per_step) / W * W : 0;
     wh = std::max<long long>(W, std::min(wh, whole));
@@ -186,11 +197,11 @@ Shape default_shape(const Plan &pl, int n_cu) {
 lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds, bool may_shrink_k,
                       bool may_shrink_w) {
     const bool ckpt = pl.adjoint == LV_ADJ_CHECKPOINT;
-    while (!shape_fits(pl, sh, max_lds) && sh.W > 8 && may_shrink_w && !ckpt) sh.W /= 2;
-    while (!shape_fits(pl, sh, max_lds) && sh.K > 1 && may_shrink_k) sh.K /= 2;
-    if (!shape_fits(pl, sh, max_lds))
+    while (!shape_fits(pl, sh, max_lds, n_cu) && sh.W > 8 && may_shrink_w && !ckpt) sh.W /= 2;
+    while (!shape_fits(pl, sh, max_lds, n_cu) && sh.K > 1 && may_shrink_k) sh.K /= 2;
+    if (!shape_fits(pl, sh, max_lds, n_cu))
         return fail(ctx, LV_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS per block (limit %zu)",
-                    std::max(lds_adj(pl, sh, table_window(pl, sh)), lds_fwd(pl, sh)), max_lds);
+                    std::max(lds_adj(pl, sh, table_window(pl, sh), n_cu), lds_fwd(pl, sh)), max_lds);
     const int bmax = lvk::adjoint_max_block(pl.precision == 64 ? 8 : 4);
     if (sh.block > bmax)
         return fail(ctx, LV_ERR_UNSUPPORTED, "the FP%d adjoint kernels run at most %d threads per block (asked %d)",
@@ -198,7 +209,8 @@ lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds,
     pl.block = sh.block;
     pl.K = sh.K;
     pl.W = table_window(pl, sh);
-    pl.WH = hist_window(pl, sh, max_lds);
+    pl.WH = hist_window(pl, sh, max_lds, n_cu);
+    pl.CH = chunk_tiles(pl, sh, n_cu);
     pl.bpc = sh.bpc;
     pl.n_tiles = (int)((pl.P + pl.block - 1) / pl.block);
     pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * sh.bpc);
@@ -225,7 +237,7 @@ std::vector<Shape> forward_candidates(const Plan &pl, const Shape &base, int n_c
             Shape sh = base;
             sh.fblock = b;
             sh.fbpc = c;
-            if (!shape_fits(pl, sh, max_lds)) continue;
+            if (!shape_fits(pl, sh, max_lds, n_cu)) continue;
             out.push_back(sh);
         }
     }
@@ -247,7 +259,7 @@ std::vector<Shape> adjoint_candidates(const Plan &pl, const Shape &base, int n_c
                     sh.K = k;
                     sh.W = w;
                     sh.bpc = c;
-                    if (!shape_fits(pl, sh, max_lds)) continue;
+                    if (!shape_fits(pl, sh, max_lds, n_cu)) continue;
                     out.push_back(sh);
                 }
             }
@@ -324,6 +336,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     pl.adjoint = o.adjoint;
     pl.seg = o.ckpt_every;
     pl.profile = o.profile ? 1 : 0;
+    pl.dense = o.dense_adjoint ? 1 : 0;
     pl.G = (int)G;
     pl.Q = 2 * pl.n_opt + 1 + pl.G;
 
@@ -501,6 +514,8 @@ lvk::Args make_args(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *
     a.W = pl.W;
     a.WH = pl.WH;
     a.K = pl.K;
+    a.CH = pl.CH;
+    a.dense = pl.dense;
     a.seg = pl.seg;
     return a;
 }
@@ -639,9 +654,9 @@ void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
 std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf, bool adjoint) {
     std::string k;
     char buf[128];
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I, pl.J,
-             pl.N, pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
-             pl.blocks, pl.W, pl.WH, pl.K, pl.fblock, pl.fblocks, pl.spot, pl.dt, n_surf);
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I,
+             pl.J, pl.N, pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
+             pl.blocks, pl.W, pl.WH, pl.K, pl.CH, pl.dense, pl.fblock, pl.fblocks, pl.spot, pl.dt, n_surf);
     k += buf;
     k += adjoint ? "A|" : "F|";
     for (int i = 0; i < n_ptrs; ++i) {
@@ -653,10 +668,10 @@ std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf
 
 std::string tune_key(const Plan &pl, bool adjoint) {
     char buf[256];
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N,
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N,
              pl.axis, pl.P, pl.precision, adjoint ? pl.adjoint : LV_ADJ_NONE, pl.seg, pl.n_opt,
              pl.n_taps, pl.user.block, pl.user.K, pl.user.W, pl.user.bpc, pl.user.fblock,
-             pl.user.fbpc, (int)pl.profile);
+             pl.user.fbpc, (int)pl.profile, pl.dense);
     return buf;
 }
 

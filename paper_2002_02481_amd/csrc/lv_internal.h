@@ -44,6 +44,8 @@ struct Args {
     int W;                      // steps per LDS table window (multiple of 4)
     int WH;                     // steps per gradient-histogram window (multiple of W)
     int K;                      // privatised histogram copies
+    int CH;                     // reverse kernel: path tiles per live-path list
+    int dense;                  // reverse kernel: sweep every path, not only live ones
     int seg;                    // checkpoint segment (steps)
 };
 
@@ -54,8 +56,8 @@ enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };
 constexpr int adjoint_max_block(int real_bytes) { return real_bytes == 8 ? 512 : 1024; }
 
 // LDS bytes a kernel variant needs for the given shape (W table steps, WH
-// histogram steps).
-size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K);
+// histogram steps, CH tiles per live-path list).
+size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K, int CH);
 // Largest fixed-point term the gradient histogram accepts, for the given shape.
 __host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P);
 

@@ -159,11 +159,12 @@ __device__ __forceinline__ T ldu(const T *p) {
 // LDS carve-up, shared by the kernels and the host planner.
 // --------------------------------------------------------------------------
 struct Lds {
-    size_t g64, wpart, wlam, tab, hist, total;
+    size_t g64, wpart, wlam, tab, hist, live, total;
 };
 
+// CH: path tiles per live-path list of the stored reverse kernel.
 __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes, int I, int J,
-                                          int n_opt, int wpb, int W, int WH, int K) {
+                                          int n_opt, int wpb, int W, int WH, int K, int CH) {
     Lds L{};
     size_t off = 0;
     const bool grad = variant == REV_STORED || variant == FUSED_CKPT;
@@ -179,13 +180,16 @@ __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes,
     off += align16((size_t)tab_bufs * W * I * 2 * rbytes);
     L.hist = off;
     off += grad ? align16((size_t)WH * K * (I + 1) * accbytes) : 0;   // rows of I + 1 words
+    L.live = off;
+    off += variant == REV_STORED ? align16(((size_t)CH * wpb * 64 + 16) * 4) : 0;   // list + wave counts
     L.total = off;
     return L;
 }
 
-size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K) {
+size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K,
+                 int CH) {
     const int rb = precision == 64 ? 8 : 4;
-    return lds_layout(variant, rb, rb, I, J, n_opt, block / 64, W, WH, K).total;
+    return lds_layout(variant, rb, rb, I, J, n_opt, block / 64, W, WH, K, CH).total;
 }
 
 __host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P) {
@@ -444,7 +448,7 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int I = a.I, N = a.N, W = a.W, nW = (N + W - 1) / W;
     const Lds lay = lds_layout(STORE ? FWD_STORE : FWD_PRICE, sizeof(R), sizeof(R), I, a.J, a.n_opt,
-                               wpb, W, a.WH, a.K);
+                               wpb, W, a.WH, a.K, a.CH);
     double *wpart = (double *)(smem + lay.wpart);
     R *tuse = (R *)(smem + lay.tab), *tnext = tuse + 2 * W * I;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
@@ -527,17 +531,40 @@ __global__ void __launch_bounds__(1024) k_fwd(Args a) {
 // Steps per state block of the reverse sweep (the table window is a multiple of it).
 constexpr int RB = 8;
 
+// Whether path p can have a nonzero adjoint: some option with a nonzero cotangent
+// is in the money at its maturity (the seed test of the sweep, on the stored state).
+// A path for which this fails has lambda = 0 at every step and contributes exactly
+// nothing to the gradient or to delta.
+template <typename R>
+__device__ bool path_live(const Args &a, const R *Y, size_t P, size_t p) {
+    for (int t = 0; t < a.n_taps; ++t) {
+        const int n = a.tap_step[t];
+        const R y = Y[(size_t)(n - 1) * P + p];
+        const double Sd = (double)((R)a.spot * Math<R>::ex(y));
+        const int k0 = ldu(a.tap_first + t), kc = ldu(a.tap_count + t);
+        for (int q = 0; q < kc; ++q) {
+            const int k = k0 + q;
+            if (ldu(a.cot + ldu(a.opt_orig + k)) == 0.0) continue;
+            const double K = ldu(a.opt_strike + k);
+            if (ldu(a.opt_put + k) ? (Sd < K) : (Sd > K)) return true;
+        }
+    }
+    return false;
+}
+
 template <typename R, int AXIS, bool MAGIC>
 __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int I = a.I, J = a.J, N = a.N, W = a.W, WH = a.WH, G = I * J, nW = (N + W - 1) / W;
-    const Lds lay = lds_layout(REV_STORED, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, W, WH, a.K);
+    const Lds lay = lds_layout(REV_STORED, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, W, WH, a.K, a.CH);
     double *g64 = (double *)(smem + lay.g64);
     double *wlam = (double *)(smem + lay.wlam);
     R *tuse = (R *)(smem + lay.tab), *tnext = tuse + 2 * W * I;
     Acc *H = (Acc *)(smem + lay.hist);
+    int *list = (int *)(smem + lay.live);   // live paths of a chunk, as tile-in-chunk * block + lane
+    int *wcnt = list + a.CH * blockDim.x;   // per-wave live counts
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < WH * a.K * (I + 1); e += blockDim.x) H[e] = 0;
@@ -549,7 +576,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     const double scd = ldexp(1.0, F), inv_sc = ldexp(1.0, -F);
     const R hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
     const R spot = (R)a.spot, amax = (R)(I - 1);
-    const int n_groups = (N + 3) >> 2, K = a.K, KI1 = K * (I + 1);
+    const int K = a.K, KI1 = K * (I + 1), B = gridDim.x, T = blockDim.x;
     Acc *Hl = H + (tid % K) * (I + 1);   // this lane's copy of a histogram row
     const R *Y = (const R *)a.states;
     const size_t P = (size_t)a.P;
@@ -561,105 +588,131 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
         stg.commit(a, tnext);
     }
 
-    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-        const bool more = tile + (int)gridDim.x < a.n_tiles;
-        const long long p = (long long)tile * blockDim.x + tid;
-        const bool active = p < a.P;
-        const size_t pc = active ? (size_t)p : P - 1;     // inactive lanes read a valid path
-        R lam = 0;   // the adjoint of y, times 2^F
-        R y_next = Y[(size_t)(N - 1) * P + pc];
-        int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
-        int hcur = (N - 1) / WH;
-        // States by blocks of RB steps (RB/4 groups of four): cur[k] = y_{b RB + k}
-        // (plane b RB + k - 1; y_0 = 0 is set where it is used).  The next block's
-        // states are loaded at the start of a block, so loads have a whole block
-        // of compute to arrive.
-        R cur[RB], nxt[RB];
-        auto load_block = [&](int b, R(&y)[RB]) {
-#pragma unroll
-            for (int k = 0; k < RB; ++k) {
-                const int pl = min(max(b * RB + k - 1, 0), N - 1);
-                y[k] = Y[(size_t)pl * P + pc];
+    // The block's path tiles b, b + B, ... are taken CH at a time: their live paths
+    // (all paths when a.dense is set) are listed in path order, then swept in passes
+    // of T lanes; each pass is folded like a tile.
+    for (int c0 = blockIdx.x; c0 < a.n_tiles; c0 += a.CH * B) {
+        __syncthreads();   // the previous chunk's list is no longer read
+        int n_live = 0;
+        for (int k = 0; k < a.CH; ++k) {
+            const int t = c0 + k * B;
+            if (t >= a.n_tiles) break;
+            const long long p = (long long)t * T + tid;
+            const bool live = p < a.P && (a.dense || path_live<R>(a, Y, P, (size_t)p));
+            const unsigned long long m = __ballot(live);
+            if (lane == 0) wcnt[wave] = __popcll(m);
+            __syncthreads();
+            int off = n_live, tot = 0;
+            for (int v = 0; v < wpb; ++v) {
+                const int c = wcnt[v];
+                off += v < wave ? c : 0;
+                tot += c;
             }
-        };
-        load_block(btop, cur);
-        for (int wi = nW - 1; wi >= 0; --wi) {
-            const int ws = wi * W, we = min(N, ws + W);
-            bool pending = false;
-            if (wi != wcur) {
-                __syncthreads();   // window wi is in tnext; tuse and the histogram are idle
-                const int hi = ws / WH;
-                if (hi != hcur) {
-                    fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
-                    hcur = hi;
-                }
-                R *t = tuse;
-                tuse = tnext;
-                tnext = t;
-                wcur = wi;
-                const int nx = wi > 0 ? wi - 1 : (more ? nW - 1 : -1);
-                if (nx >= 0 && nW > 1) {
-                    stg.issue(a, nx * W, min(W, N - nx * W));
-                    pending = true;
-                }
-            }
-            const int hbase = hcur * WH;
-            // one group of four steps n0 .. n0+3 whose states are y[0..3]
-            auto group = [&](int n0, const R *y, auto full_tag) {
-                constexpr bool FULL = decltype(full_tag)::value;
-                const int wn0 = n0 - ws, hn0 = n0 - hbase;
-                Look<R> L[4];
-                R cc[4], dsd[4], yup[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (FULL || n0 + r < N) {
-                        const R yr = (n0 + r == 0) ? (R)0 : y[r];
-                        yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : y[r + 1];
-                        L[r] = lookup<R, AXIS>(yr, tuse + 2 * (wn0 + r) * I, inv_du, a_off, amax,
-                                               spot);
-                        cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
-                        R d = L[r].in ? L[r].d * inv_du : (R)0;
-                        if (AXIS == 0) d *= L[r].S;
-                        dsd[r] = d;
-                    }
-                }
-#pragma unroll
-                for (int r = 3; r >= 0; --r) {
-                    const int n = n0 + r;
-                    if (FULL || n < N) {
-                        if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R>(a, tap, yup[r], lam, scd);
-                            if (!active) lam = 0;
-                            --tap;
-                            cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
-                        }
-                        const R x = lam * cc[r];   // lam carries 2^F: x is the fixed-point term
-                        lam = fma(x, dsd[r], lam);
-                        scatter<R>(a, Hl + (hn0 + r) * KI1, g64, n, L[r], x, qm, magic, inv_sc);
-                    }
-                }
-                if (FULL || n0 < N) y_next = (n0 == 0) ? (R)0 : y[0];
-            };
-            auto block = [&](int b, auto full_tag) {
-                load_block(max(b - 1, 0), nxt);
-#pragma unroll
-                for (int q = RB / 4 - 1; q >= 0; --q) group(b * RB + 4 * q, cur + 4 * q, full_tag);
-#pragma unroll
-                for (int k = 0; k < RB; ++k) cur[k] = nxt[k];
-            };
-            // The window's first block runs on its own (the horizon's top block may
-            // be partial), then the next table window is committed, then the rest.
-            const int blo = ws / RB;
-            int b = (we - 1) / RB;
-            if (wi == nW - 1) block(b, std::false_type{});
-            else block(b, std::true_type{});
-            if (pending) stg.commit(a, tnext);
-            for (--b; b >= blo; --b) block(b, std::true_type{});
+            if (live) list[off + __popcll(m & ((1ull << lane) - 1))] = k * T + tid;
+            n_live += tot;
+            __syncthreads();
         }
-        __syncthreads();
-        fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
-        const double l0 = wave_sum(active ? (double)lam * inv_sc : 0.0);
-        if (lane == 0) wlam[wave] += l0;
+        for (int base = 0; base < n_live; base += T) {
+            const bool more = base + T < n_live || c0 + a.CH * B < a.n_tiles;
+            const bool active = base + tid < n_live;
+            const int e = list[active ? base + tid : 0];   // inactive lanes read a live path
+            const int ek = e / T;
+            const size_t pc = (size_t)(c0 + ek * B) * T + (size_t)(e - ek * T);
+            R lam = 0;   // the adjoint of y, times 2^F
+            R y_next = Y[(size_t)(N - 1) * P + pc];
+            int tap = a.n_taps - 1, cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+            int hcur = (N - 1) / WH;
+            // States by blocks of RB steps (RB/4 groups of four): cur[k] = y_{b RB + k}
+            // (plane b RB + k - 1; y_0 = 0 is set where it is used).  The next block's
+            // states are loaded at the start of a block, so loads have a whole block
+            // of compute to arrive.
+            R cur[RB], nxt[RB];
+            auto load_block = [&](int b, R(&y)[RB]) {
+#pragma unroll
+                for (int k = 0; k < RB; ++k) {
+                    const int pl = min(max(b * RB + k - 1, 0), N - 1);
+                    y[k] = Y[(size_t)pl * P + pc];
+                }
+            };
+            load_block(btop, cur);
+            for (int wi = nW - 1; wi >= 0; --wi) {
+                const int ws = wi * W, we = min(N, ws + W);
+                bool pending = false;
+                if (wi != wcur) {
+                    __syncthreads();   // window wi is in tnext; tuse and the histogram are idle
+                    const int hi = ws / WH;
+                    if (hi != hcur) {
+                        fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
+                        hcur = hi;
+                    }
+                    R *t = tuse;
+                    tuse = tnext;
+                    tnext = t;
+                    wcur = wi;
+                    const int nx = wi > 0 ? wi - 1 : (more ? nW - 1 : -1);
+                    if (nx >= 0 && nW > 1) {
+                        stg.issue(a, nx * W, min(W, N - nx * W));
+                        pending = true;
+                    }
+                }
+                const int hbase = hcur * WH;
+                // one group of four steps n0 .. n0+3 whose states are y[0..3]
+                auto group = [&](int n0, const R *y, auto full_tag) {
+                    constexpr bool FULL = decltype(full_tag)::value;
+                    const int wn0 = n0 - ws, hn0 = n0 - hbase;
+                    Look<R> L[4];
+                    R cc[4], dsd[4], yup[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (FULL || n0 + r < N) {
+                            const R yr = (n0 + r == 0) ? (R)0 : y[r];
+                            yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : y[r + 1];
+                            L[r] = lookup<R, AXIS>(yr, tuse + 2 * (wn0 + r) * I, inv_du, a_off, amax,
+                                                   spot);
+                            cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
+                            R d = L[r].in ? L[r].d * inv_du : (R)0;
+                            if (AXIS == 0) d *= L[r].S;
+                            dsd[r] = d;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 3; r >= 0; --r) {
+                        const int n = n0 + r;
+                        if (FULL || n < N) {
+                            if (n + 1 == cur_tap) {
+                                lam = rev_seeds<R>(a, tap, yup[r], lam, scd);
+                                if (!active) lam = 0;
+                                --tap;
+                                cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
+                            }
+                            const R x = lam * cc[r];   // lam carries 2^F: x is the fixed-point term
+                            lam = fma(x, dsd[r], lam);
+                            scatter<R>(a, Hl + (hn0 + r) * KI1, g64, n, L[r], x, qm, magic, inv_sc);
+                        }
+                    }
+                    if (FULL || n0 < N) y_next = (n0 == 0) ? (R)0 : y[0];
+                };
+                auto block = [&](int b, auto full_tag) {
+                    load_block(max(b - 1, 0), nxt);
+#pragma unroll
+                    for (int q = RB / 4 - 1; q >= 0; --q) group(b * RB + 4 * q, cur + 4 * q, full_tag);
+#pragma unroll
+                    for (int k = 0; k < RB; ++k) cur[k] = nxt[k];
+                };
+                // The window's first block runs on its own (the horizon's top block may
+                // be partial), then the next table window is committed, then the rest.
+                const int blo = ws / RB;
+                int b = (we - 1) / RB;
+                if (wi == nW - 1) block(b, std::false_type{});
+                else block(b, std::true_type{});
+                if (pending) stg.commit(a, tnext);
+                for (--b; b >= blo; --b) block(b, std::true_type{});
+            }
+            __syncthreads();
+            fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
+            const double l0 = wave_sum(active ? (double)lam * inv_sc : 0.0);
+            if (lane == 0) wlam[wave] += l0;
+        }
     }
     __syncthreads();
     double *out = a.part + (size_t)blockIdx.x * a.Q;
@@ -688,7 +741,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int I = a.I, J = a.J, N = a.N, G = I * J, WH = a.WH;
-    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, WH, a.K);
+    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, WH, a.K, a.CH);
     double *g64 = (double *)(smem + lay.g64);
     double *wpart = (double *)(smem + lay.wpart);
     double *wlam = (double *)(smem + lay.wlam);
@@ -963,7 +1016,7 @@ __global__ void k_debug_normals(unsigned long long seed, unsigned long long p0, 
 template <typename R>
 static size_t lds_of(int variant, const Args &a, int block, int W) {
     const int rb = sizeof(R);
-    return lds_layout(variant, rb, rb, a.I, a.J, a.n_opt, block / 64, W, a.WH, a.K).total;
+    return lds_layout(variant, rb, rb, a.I, a.J, a.n_opt, block / 64, W, a.WH, a.K, a.CH).total;
 }
 
 // Blocks above 64 KiB of LDS (gfx950 has 160 KiB per CU) must be allowed per kernel.

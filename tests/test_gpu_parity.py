@@ -182,6 +182,31 @@ def test_zero_buckets_exact(lv, ctx, orc):
         assert_parity(got, ref, precision, f"zero buckets {precision}")
 
 
+def test_live_path_sweep_matches_dense(lv, ctx):
+    """The stored reverse sweep visits only paths with an option in the money at its
+    maturity (every other path has a zero adjoint); sweeping every path instead
+    gives the same gradient and delta up to FP64 summation order, and the same
+    prices.  A single call (about half its paths are dead) and a 64-option book
+    whose cotangents are zero for every third option."""
+    small = W.small_call()
+    b = W.book64()
+    w = np.where(np.arange(b.n) % 3 == 0, 0.0, b.weight)
+    cases = [(small.surface, small.book, small.n_paths, small.n_steps),
+             (W.book_surface(0), W.Book(b.is_put, b.strike, b.maturity, w), 1 << 15, 156)]
+    for surf, bk, P, N in cases:
+        for precision in (32, 64):
+            sp = gpu_run(lv, ctx, surf, bk, P, N, 3, precision=precision)
+            de = gpu_run(lv, ctx, surf, bk, P, N, 3, precision=precision, dense_adjoint=True)
+            assert np.array_equal(sp["price"], de["price"])
+            gmax = np.abs(de["grad"]).max()
+            dg = np.abs(sp["grad"] - de["grad"]).max()
+            say(f"  live vs dense, {surf.sigma.shape} FP{precision}: max|dgrad|/max|g| {dg / gmax:.3g}, "
+                f"delta {sp['delta']:.12g} vs {de['delta']:.12g}")
+            assert dg <= 1e-12 * gmax
+            assert np.array_equal(sp["grad"] == 0.0, de["grad"] == 0.0)
+            assert abs(sp["delta"] - de["delta"]) <= 1e-12 * abs(de["delta"])
+
+
 def test_block_shapes_agree(lv, ctx, orc):
     """Every launch shape computes the same thing: block sizes, histogram copies,
     windows and grid sizes all pass the same parity bar."""
