@@ -1,14 +1,15 @@
 """Benchmark: path-steps/s for price + full vol-grid adjoint on one MI355X.
 
-A step is one pass of the whole path over one batch: Philox normals, LDS vol
-lookup, log-Euler stepping with stored states, payoff and FP64 reductions, the
-reverse sweep with the fixed-point LDS gradient histogram, and the fixed-order
-merge -- for the workload of the paper's timing run: one call, 2^19 paths
-(the paper's 500K), 156 weekly steps, a 60 x 30 = 1800-node grid, FP32 stepping.
+A step is one pass of the whole path over one batch: the per-step vol table,
+Philox normals, LDS vol lookup, log-Euler stepping with stored states, payoff and
+FP64 reductions, the reverse sweep (over the paths whose adjoint is not zero) with
+the fixed-point LDS gradient histogram, and the fixed-order merge -- for the
+workload of the paper's timing run: one call, 2^19 paths (the paper's 500K), 156
+weekly steps, a 60 x 30 = 1800-node grid, FP32 stepping.
 
-Prints one JSON line.  Also reports the FP64 GPU variant, the forward-only and
-checkpointed variants, their accuracy against each other, the roofline of the
-dominant kernel and the CPU oracle timed on a bounded sample.
+Prints one JSON line.  Also reports the FP64 GPU variant, the forward-only,
+checkpointed and every-path-reverse variants, their accuracy against each other,
+the roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -20,17 +21,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X public peaks
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 3.93e13 vector lane-slots/s
+# (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and packed FP32 as 2 lanes; the
+# kernels are built without packed FP32).  HBM3E 8 TB/s.
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3          # FP32 vector
-PEAK_VALU_TOPS = PEAK_FP32_TFLOPS / 2.0   # 256 CUs x 128 FP32 lanes/clk x 2.4 GHz (lane-ops/s)
+PEAK_SLOTS_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic work per path-step ("Roofline"): VALU lane-operations
-# of the method's arithmetic, and HBM bytes of the stored states.
-OPS_FWD = 34.0      # Philox/4 (15) + uniforms (3) + Box-Muller (4) + lookup (9) + Euler (2) + store (1)
-OPS_REV = 32.0      # load (1) + lookup (9) + dy/dsigma (4) + slope (4) + adjoint (2) + scatter (12)
+# Algorithmic work per path-step on the log-spot axis, in VALU issue slots: each
+# operation of the method weighted by its issue cost on gfx950 (full rate 1;
+# 32x32->64 multiply 2.4; transcendental 3.1), the breakdown in the design doc.
+SLOTS_FWD = 37.7    # Philox/4 17 + uniforms 3 + Box-Muller 7.7 + lookup 7 + Euler 2 + store 1
+SLOTS_REV = 26.1    # per live path-step: load 1 + lookup 7 + slope 4 + c_n 6.1 + adjoint 2 + scatter 6
 BYTES_FWD = 4.0     # one FP32 state written per path-step
-BYTES_REV = 4.0     # one FP32 state read per path-step
+BYTES_REV = 4.0     # one FP32 state read per live path-step
 
 
 def measured_traffic(kernel: str):
@@ -117,35 +120,54 @@ def main():
             opts.setdefault(k, v)
         return base_run(out=out, **opts)
 
+    # fraction of paths the reverse sweep visits: those ending in the money
+    _, _, states = lv.forward_dev(sig, 100.0, strikes, mats, P, N, wl.seed, spot_axis=s.spot_axis,
+                                  time_axis=s.time_axis, ctx=ctx)
+    y_last = states.view(torch.float32).view(N, P)[N - 1]
+    live_frac = float((100.0 * torch.exp(y_last) > float(strikes[0])).double().mean())
+    del states, y_last
+    torch.cuda.synchronize()
+
+    # warmup: every kernel timed with HIP events, to find the dominant kernel
     for _ in range(args.warmup):
         run(out=out, profile=True)
     torch.cuda.synchronize()
-    ctx.kernel_times(reset=True)
+    warm = ctx.kernel_times(reset=True)
+    warm_avg = {k: (ms / n if n else 0.0) for k, (ms, n) in warm.items()}
+    dom = max(("fwd", "rev"), key=lambda k: warm_avg[k])
+    dom_bit = 1 << lv._lib.KERNEL_KINDS.index(dom)
 
+    # timed region: events on the dominant kernel only (a timed dispatch waits for its
+    # timestamp, so timing every kernel would slow the step it measures)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        run(out=out, profile=True)
+        run(out=out, profile=True, profile_kinds=dom_bit)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = P * N / (ms_per_step * 1e-3)
     times = ctx.kernel_times(reset=True)
-    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in times.items()}
+    avg = dict(warm_avg)
+    avg[dom] = times[dom][0] / times[dom][1]
 
-    # roofline of the dominant kernel
-    dom = max(("fwd", "rev"), key=lambda k: avg[k])
-    units = P * N
-    ops = (OPS_FWD if dom == "fwd" else OPS_REV) * units
+    # roofline of the dominant kernel: algorithmic slots per launch / its mean duration
+    units = P * N * (1.0 if dom == "fwd" else live_frac)     # path-steps of work per launch
+    slots = (SLOTS_FWD if dom == "fwd" else SLOTS_REV) * units
     byts = (BYTES_FWD if dom == "fwd" else BYTES_REV) * units
-    achieved_tops = ops / (avg[dom] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved_tops, 3),
-                "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "frac": round(achieved_tops / PEAK_VALU_TOPS, 4),
+    achieved = slots / (avg[dom] * 1e-3) / 1e12
+    frac_of = {k: round((SLOTS_FWD * P * N if k == "fwd" else SLOTS_REV * P * N * live_frac)
+                        / (avg[k] * 1e-3) / 1e12 / PEAK_SLOTS_T, 4) for k in ("fwd", "rev")}
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                "peak": round(PEAK_SLOTS_T, 3), "unit": "Tops/s", "frac": round(achieved / PEAK_SLOTS_T, 4),
                 "traffic": measured_traffic(dom),
-                "ops_per_path_step": OPS_FWD if dom == "fwd" else OPS_REV,
+                "slots_per_path_step": SLOTS_FWD if dom == "fwd" else SLOTS_REV,
+                "path_steps_per_launch": units, "live_fraction": round(live_frac, 5),
+                "frac_by_kernel": frac_of,
                 "hbm_achieved_GBs": round(byts / (avg[dom] * 1e-3) / 1e9, 1),
                 "hbm_frac": round(byts / (avg[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                "avg_ms": {k: round(v, 5) for k, v in avg.items() if v}}
+                "avg_ms": {k: round(v, 5) for k, v in avg.items() if v},
+                "avg_ms_from": f"{dom}: HIP events over the timed region; others: events over the warmup steps"}
 
     price32, se32, grad32, delta32 = [t.cpu().numpy().copy() for t in out]
     result = {
@@ -155,7 +177,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded 60x30 local-vol surface, Philox streams)",
         "config": {"workload": wl.name, "paths": P, "steps": N, "grid": list(s.sigma.shape),
-                   "options": 1, "adjoint": "stored", "parallelism": "none", "launch": shape},
+                   "options": 1, "adjoint": "stored, live paths", "parallelism": "none", "launch": shape},
         "roofline": roofline,
     }
 
@@ -177,6 +199,10 @@ def main():
         msc, oc = timed(max(3, args.steps // 2), adjoint="checkpoint")
         variants["fp32_checkpoint"] = {"ms_per_step": msc, "value": P * N / (msc * 1e-3),
                                        "max_bucket_err_vs_stored": float(np.abs(oc[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
+        msd, od = timed(max(3, args.steps // 2), dense_adjoint=True)
+        variants["fp32_every_path_reverse"] = {
+            "ms_per_step": msd, "value": P * N / (msd * 1e-3),
+            "max_bucket_diff_vs_live": float(np.abs(od[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
         result["variants"] = variants
         result["accuracy"] = {
             "fp32_vs_fp64_gpu_price_abs": float(abs(price32.ravel()[0] - p64.ravel()[0])),

@@ -121,6 +121,9 @@ typedef struct {
     int32_t dense_adjoint;  /* stored adjoint: 1 = sweep every path back; 0 (default) = sweep only
                                the paths with an option in the money at its maturity, since every
                                other path has a zero adjoint and contributes exactly nothing */
+    int32_t profile_kinds;  /* with profile: bit (1 << LV_K_*) set = time that kernel kind; 0 = all.
+                               A timed dispatch waits for its timestamp (several microseconds),
+                               so timing only the kernel of interest keeps the others' pace */
 } lv_opts;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`

@@ -76,12 +76,12 @@ class _Book:
 
 def make_opts(precision=32, adjoint="stored", ckpt_every=16, use_graph=False, block=0,
               blocks_per_cu=0, copies=0, window=0, profile=False, autotune=False, fwd_block=0,
-              fwd_blocks_per_cu=0, dense_adjoint=False) -> lv_opts:
+              fwd_blocks_per_cu=0, dense_adjoint=False, profile_kinds=0) -> lv_opts:
     adj = ADJOINT[adjoint] if isinstance(adjoint, str) else int(adjoint)
     return lv_opts(int(precision), adj, int(ckpt_every), int(bool(use_graph)), int(block),
                    int(blocks_per_cu), int(copies), int(window), int(bool(profile)),
                    int(bool(autotune)), int(fwd_block), int(fwd_blocks_per_cu),
-                   int(bool(dense_adjoint)))
+                   int(bool(dense_adjoint)), int(profile_kinds))
 
 
 def option_order(maturities, n_steps) -> np.ndarray:

@@ -40,8 +40,8 @@ struct Plan {
     int n_opt = 0, n_taps = 0;
     std::vector<int> tj, cell_lo, tap_step, tap_first, tap_count, opt_put, opt_orig;
     std::vector<double> ta, opt_strike, weight;
-    int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;
-    int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, S = 32, bpc = 2, CH = 1;
+    int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;   // profile: kinds to time (bits)
+    int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, bpc = 2, CH = 1;
     int dense = 0;   // reverse kernel sweeps every path (not only those with a nonzero adjoint)
     int fblock = 256, fblocks = 0, f_n_tiles = 0, fbpc = 2;
     int G = 0, Q = 0;
@@ -58,7 +58,7 @@ struct lv_ctx {
     int n_cu = 256;
     size_t max_lds = 65536;
     std::string err = "no error";
-    Buf planbuf, part, seg, states, ckpt, sig_stage, out_stage, gtab;
+    Buf planbuf, part, states, ckpt, sig_stage, out_stage, gtab;
     std::vector<char> plan_bytes;     // what planbuf holds
     lv_run_info info{};
     int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
@@ -218,9 +218,6 @@ lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds,
     pl.fbpc = sh.fbpc;
     pl.f_n_tiles = (int)((pl.P + pl.fblock - 1) / pl.fblock);
     pl.fblocks = (int)std::min<long long>(pl.f_n_tiles, (long long)n_cu * sh.fbpc);
-    // two merge levels of about sqrt(records) loads each
-    const int recs = std::max(pl.blocks, pl.fblocks);
-    pl.S = std::max(1, std::min(recs, (int)std::lround(std::sqrt((double)recs))));
     return LV_OK;
 }
 
@@ -335,7 +332,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     pl.precision = o.precision;
     pl.adjoint = o.adjoint;
     pl.seg = o.ckpt_every;
-    pl.profile = o.profile ? 1 : 0;
+    pl.profile = o.profile ? (o.profile_kinds ? o.profile_kinds : (1 << LV_K_COUNT) - 1) : 0;
     pl.dense = o.dense_adjoint ? 1 : 0;
     pl.G = (int)G;
     pl.Q = 2 * pl.n_opt + 1 + pl.G;
@@ -532,7 +529,6 @@ lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
     lv_status st;
     if ((st = ensure_table(ctx, pl)) != LV_OK) return st;
     if ((st = ensure(ctx, ctx->part, (size_t)std::max(pl.blocks, pl.fblocks) * pl.Q * 8)) != LV_OK) return st;
-    if ((st = ensure(ctx, ctx->seg, (size_t)pl.S * pl.Q * 8)) != LV_OK) return st;
     if (adjoint && pl.adjoint == LV_ADJ_STORED) {
         const size_t b = (size_t)pl.N * (size_t)pl.P * real_bytes(pl.precision);
         if ((st = ensure(ctx, ctx->states, b)) != LV_OK) return st;
@@ -556,17 +552,14 @@ hipEvent_t take_event(lv_ctx *ctx) {
     return e;
 }
 
-// Launch `fn` on the context's stream, bracketed by events when profiling.
+// Launch `fn` on the context's stream; when profiling, with a pair of events
+// attached to its dispatches (no extra packets between kernels).
 template <typename Fn>
-hipError_t timed(lv_ctx *ctx, bool profile, int kind, Fn fn) {
-    if (!profile) return fn();
+hipError_t timed(lv_ctx *ctx, int profile, int kind, Fn fn) {
+    if (!(profile & (1 << kind))) return fn(lvk::Ev{});
     hipEvent_t a = take_event(ctx), b = take_event(ctx);
     if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, ctx->stream());
-    if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, ctx->stream());
+    hipError_t e = fn(lvk::Ev{a, b});
     if (e != hipSuccess) return e;
     ctx->pending.push_back({a, b, kind});
     return hipSuccess;
@@ -596,34 +589,33 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
     a.part = (double *)ctx->part.p;
     a.states = ctx->states.p;
     a.ckpt = ctx->ckpt.p;
-    const bool prof = pl.profile && !capturing;
-    hipError_t e = timed(ctx, prof, LV_K_TABLE, [&] { return lvk::launch_table(a, pl.precision, st); });
+    const int prof = capturing ? 0 : pl.profile;
+    hipError_t e = timed(ctx, prof, LV_K_TABLE, [&](lvk::Ev ev) { return lvk::launch_table(a, pl.precision, st, ev); });
     if (e != hipSuccess) return e;
     lvk::Args af = a;                 // the forward kernel's own tiling
     af.n_tiles = pl.f_n_tiles;
     if (!adjoint) {
-        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(af, pl.precision, false, pl.fblocks, pl.fblock, st); });
+        e = timed(ctx, prof, LV_K_FWD, [&](lvk::Ev ev) { return lvk::launch_fwd(af, pl.precision, false, pl.fblocks, pl.fblock, st, ev); });
         if (e != hipSuccess) return e;
-        return timed(ctx, prof, LV_K_MERGE, [&] {
-            return lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S,
-                                     pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, nullptr,
-                                     nullptr, st);
+        return timed(ctx, prof, LV_K_MERGE, [&](lvk::Ev ev) {
+            return lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, pl.n_opt, pl.G, t.opt_orig, pl.P,
+                                     pl.spot, price, stderr_, nullptr, nullptr, st, ev);
         });
     }
     int b_pay = pl.blocks;
     if (pl.adjoint == LV_ADJ_STORED) {
-        e = timed(ctx, prof, LV_K_FWD, [&] { return lvk::launch_fwd(af, pl.precision, true, pl.fblocks, pl.fblock, st); });
+        e = timed(ctx, prof, LV_K_FWD, [&](lvk::Ev ev) { return lvk::launch_fwd(af, pl.precision, true, pl.fblocks, pl.fblock, st, ev); });
         if (e != hipSuccess) return e;
-        e = timed(ctx, prof, LV_K_REV, [&] { return lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st); });
+        e = timed(ctx, prof, LV_K_REV, [&](lvk::Ev ev) { return lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st, ev); });
         if (e != hipSuccess) return e;
         b_pay = pl.fblocks;
     } else {
-        e = timed(ctx, prof, LV_K_FUSED, [&] { return lvk::launch_fused_ckpt(a, pl.precision, pl.blocks, pl.block, st); });
+        e = timed(ctx, prof, LV_K_FUSED, [&](lvk::Ev ev) { return lvk::launch_fused_ckpt(a, pl.precision, pl.blocks, pl.block, st, ev); });
         if (e != hipSuccess) return e;
     }
-    e = timed(ctx, prof, LV_K_MERGE, [&] {
-        return lvk::launch_merge(a.part, b_pay, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
-                                 pl.G, t.opt_orig, pl.P, pl.spot, price, stderr_, grad, delta, st);
+    e = timed(ctx, prof, LV_K_MERGE, [&](lvk::Ev ev) {
+        return lvk::launch_merge(a.part, b_pay, pl.blocks, pl.Q, pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot,
+                                 price, stderr_, grad, delta, st, ev);
     });
     return e;
 }
@@ -777,8 +769,8 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
         return LV_OK;
     }
     const void *ptrs[] = {sigmas_dev, prices, stderrs, grads, deltas, ctx->planbuf.p, ctx->part.p,
-                          ctx->seg.p, ctx->states.p, ctx->ckpt.p, ctx->gtab.p};
-    std::string key = graph_key(pl, ptrs, 11, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
+                          ctx->states.p, ctx->ckpt.p, ctx->gtab.p};
+    std::string key = graph_key(pl, ptrs, 10, n_surf, adjoint) + std::string(ctx->plan_bytes.begin(), ctx->plan_bytes.end());
     bool replay = ctx->graph_exec && key == ctx->graph_key;
     if (!replay) {
         if (ctx->graph_exec) {
@@ -854,7 +846,7 @@ void lv_destroy(lv_ctx *ctx) {
         ctx->event_pool.push_back(t.b);
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-    Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->seg, &ctx->states, &ctx->ckpt,
+    Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->states, &ctx->ckpt,
                    &ctx->sig_stage, &ctx->out_stage, &ctx->gtab};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -976,8 +968,8 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
     hipError_t e = lvk::launch_table(a, pl.precision, st);
     if (e == hipSuccess) e = lvk::launch_fwd(a, pl.precision, true, pl.fblocks, pl.fblock, st);
     if (e == hipSuccess)
-        e = lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
-                              pl.G, t.opt_orig, pl.P, pl.spot, price_dev, std_err_dev, nullptr, nullptr, st);
+        e = lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot,
+                              price_dev, std_err_dev, nullptr, nullptr, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     record_info(ctx, pl, false, false);
     return LV_OK;
@@ -1012,9 +1004,8 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     if (e == hipSuccess) e = lvk::launch_rev(a, pl.precision, pl.blocks, pl.block, st);
     double *scratch = (double *)ctx->out_stage.p;
     if (e == hipSuccess)
-        e = lvk::launch_merge(a.part, pl.blocks, pl.blocks, pl.Q, (double *)ctx->seg.p, pl.S, pl.n_opt,
-                              pl.G, t.opt_orig, pl.P, pl.spot, scratch, scratch + pl.n_opt, grad_dev,
-                              delta_dev, st);
+        e = lvk::launch_merge(a.part, pl.blocks, pl.blocks, pl.Q, pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot,
+                              scratch, scratch + pl.n_opt, grad_dev, delta_dev, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     record_info(ctx, pl, true, false);
     ctx->info.fixed_point_bits = -1000;   // depends on the device cotangent

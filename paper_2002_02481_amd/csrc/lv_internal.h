@@ -61,18 +61,24 @@ size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block,
 // Largest fixed-point term the gradient histogram accepts, for the given shape.
 __host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P);
 
+// Optional timing events taken from a launch's own dispatch (start of the first
+// kernel, end of the last), so timing adds no packets between kernels.
+struct Ev {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Vol table of every step into a.gtab (run before the pricing kernels).
-hipError_t launch_table(const Args &a, int precision, hipStream_t st);
+hipError_t launch_table(const Args &a, int precision, hipStream_t st, Ev ev = {});
 hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block,
-                      hipStream_t st);
-hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st);
-hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st);
+                      hipStream_t st, Ev ev = {});
+hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st, Ev ev = {});
+hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st,
+                             Ev ev = {});
 // Fixed-order merge of part [records][Q] into final outputs: payoff entries over
 // the first B_pay records, the rest over the first B_grad.
-hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, double *seg, int S,
-                        int n_opt, int G, const int *opt_orig, long long P, double spot,
-                        double *price, double *stderr_, double *grad, double *delta,
-                        hipStream_t st);
+hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_opt, int G,
+                        const int *opt_orig, long long P, double spot, double *price, double *stderr_,
+                        double *grad, double *delta, hipStream_t st, Ev ev = {});
 hipError_t launch_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
                                unsigned long long p0, long long n_paths, uint32_t *out,
                                hipStream_t st);

@@ -25,6 +25,7 @@
 // combines them.
 // Terms too large for the fixed-point range take an FP64 LDS-atomic side path into
 // the block's grid.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -906,7 +907,10 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
 }
 
 // --------------------------------------------------------------------------
-// Fixed-order merge: Neumaier sums over blocks in block order, two levels.
+// Fixed-order merge of the block records: one wavefront per output; lane l takes
+// the compensated sum of records l, l + 64, l + 128, ... in order, then a fixed
+// butterfly combines the lanes.  The association is the same on every run,
+// whatever order the blocks finished in.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void neumaier(double &sum, double &comp, double x) {
     const double t = sum + x;
@@ -917,60 +921,46 @@ __device__ __forceinline__ void neumaier(double &sum, double &comp, double x) {
     sum = t;
 }
 
-// Level 1: thread (q, s) sums records [B s / S, B (s+1) / S) of entry q in record
-// order, B = the payoff kernel's grid for the payoff entries (q < n_pay) and the
-// adjoint kernel's grid for the rest; loads are issued in batches of 8 before the
-// compensated adds.
-__global__ void k_merge1(const double *part, int B_pay, int B_grad, int n_pay, int Qr, int Qm, int S,
-                         double *seg) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
-    if (q >= Qm) return;
-    const int B = q < n_pay ? B_pay : B_grad;
-    const int b0 = (int)((long long)B * s / S), b1 = (int)((long long)B * (s + 1) / S);
+__device__ __forceinline__ double record_sum(const double *part, int Q, int q, int B, int lane) {
     double sum = 0.0, comp = 0.0;
-    int b = b0;
-    for (; b + 8 <= b1; b += 8) {
+    int b = lane;
+    for (; b + 64 * 7 < B; b += 64 * 8) {   // eight loads in flight per lane
         double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = part[(size_t)(b + k) * Qr + q];
+        for (int k = 0; k < 8; ++k) v[k] = part[(size_t)(b + 64 * k) * Q + q];
 #pragma unroll
         for (int k = 0; k < 8; ++k) neumaier(sum, comp, v[k]);
     }
-    for (; b < b1; ++b) neumaier(sum, comp, part[(size_t)b * Qr + q]);
-    seg[(size_t)s * Qm + q] = sum + comp;
+    for (; b < B; b += 64) neumaier(sum, comp, part[(size_t)b * Q + q]);
+    return wave_sum(sum + comp);
 }
 
-__device__ __forceinline__ double seg_total(const double *seg, int S, int Q, int q) {
-    double sum = 0.0, comp = 0.0;
-    int s = 0;
-    for (; s + 8 <= S; s += 8) {
-        double v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = seg[(size_t)(s + k) * Q + q];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) neumaier(sum, comp, v[k]);
-    }
-    for (; s < S; ++s) neumaier(sum, comp, seg[(size_t)s * Q + q]);
-    return sum + comp;
-}
-
-// Level 2 and finalisation.
-__global__ void k_merge2(const double *seg, int S, int Q, int n_opt, int G,
-                         const int *opt_orig, long long P, double spot, double *price,
-                         double *stderr_, double *grad, double *delta) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// Output t (one per wavefront): option t's price and standard error (t < n_opt),
+// delta (t = n_opt), grid node t - n_opt - 1.  Payoff entries sum the first B_pay
+// records, the others the first B_grad.
+__global__ void k_merge(const double *part, int B_pay, int B_grad, int Q, int n_opt, int G,
+                        const int *opt_orig, long long P, double spot, double *price,
+                        double *stderr_, double *grad, double *delta) {
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const double Pd = (double)P;
     if (t < n_opt) {
-        const double s1 = seg_total(seg, S, Q, 2 * t), s2 = seg_total(seg, S, Q, 2 * t + 1);
-        const int o = opt_orig[t];
-        price[o] = s1 / Pd;
-        const double var = (s2 - s1 * s1 / Pd) / (Pd - 1.0);
-        stderr_[o] = sqrt(fmax(var, 0.0) / Pd);
+        const double s1 = record_sum(part, Q, 2 * t, B_pay, lane);
+        const double s2 = record_sum(part, Q, 2 * t + 1, B_pay, lane);
+        if (lane == 0) {
+            const int o = opt_orig[t];
+            price[o] = s1 / Pd;
+            const double var = (s2 - s1 * s1 / Pd) / (Pd - 1.0);
+            stderr_[o] = sqrt(fmax(var, 0.0) / Pd);
+        }
     } else if (t == n_opt) {
-        if (delta) *delta = seg_total(seg, S, Q, 2 * n_opt) / Pd / spot;
+        if (delta) {
+            const double s = record_sum(part, Q, 2 * n_opt, B_grad, lane);
+            if (lane == 0) *delta = s / Pd / spot;
+        }
     } else if (grad && t < n_opt + 1 + G) {
         const int q = t - n_opt - 1;
-        grad[q] = seg_total(seg, S, Q, 2 * n_opt + 1 + q) / Pd;
+        const double s = record_sum(part, Q, 2 * n_opt + 1 + q, B_grad, lane);
+        if (lane == 0) grad[q] = s / Pd;
     }
 }
 
@@ -1026,13 +1016,18 @@ static void allow_lds(Kern kernel, size_t lds) {
         (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-#define LAUNCH(kern, blocks, block, lds, st, a)                                    \
-    do {                                                                           \
-        allow_lds(kern, lds);                                                      \
-        hipLaunchKernelGGL(kern, dim3(blocks), dim3(block), lds, st, a);           \
+// Launch with the timing events ev (in scope) attached to the dispatch, if any.
+#define LAUNCH(kern, blocks, block, lds, st, a)                                                      \
+    do {                                                                                             \
+        allow_lds(kern, lds);                                                                        \
+        if (ev.start || ev.stop)                                                                     \
+            hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(block), lds, st, ev.start, ev.stop, 0, a); \
+        else                                                                                         \
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(block), lds, st, a);                         \
     } while (0)
 
-hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block, hipStream_t st) {
+hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block, hipStream_t st,
+                      Ev ev) {
     const int v = store ? FWD_STORE : FWD_PRICE;
     if (precision == 64) {
         const size_t lds = lds_of<double>(v, a, block, a.W);
@@ -1063,7 +1058,7 @@ static bool use_magic(const Args &a, int precision, int block) {
     return precision == 64 || qmax <= Math<float>::MAGIC_MAX;
 }
 
-hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st) {
+hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st, Ev ev) {
     if (precision == 64) {
         const size_t lds = lds_of<double>(REV_STORED, a, block, a.W);
         if (a.axis == 0) LAUNCH((k_rev<double, 0, true>), blocks, block, lds, st, a);
@@ -1083,51 +1078,49 @@ hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipSt
 }
 
 template <typename R, int SEG, bool MAGIC>
-static void fused_seg(const Args &a, int blocks, int block, hipStream_t st) {
+static void fused_seg(const Args &a, int blocks, int block, hipStream_t st, Ev ev) {
     const size_t lds = lds_of<R>(FUSED_CKPT, a, block, SEG);
     if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG, MAGIC>), blocks, block, lds, st, a);
     else LAUNCH((k_fused<R, 1, SEG, MAGIC>), blocks, block, lds, st, a);
 }
 
 template <typename R, bool MAGIC>
-static void fused_any(const Args &a, int blocks, int block, hipStream_t st) {
+static void fused_any(const Args &a, int blocks, int block, hipStream_t st, Ev ev) {
     switch (a.seg) {
-        case 8: fused_seg<R, 8, MAGIC>(a, blocks, block, st); break;
-        case 16: fused_seg<R, 16, MAGIC>(a, blocks, block, st); break;
-        default: fused_seg<R, 32, MAGIC>(a, blocks, block, st); break;
+        case 8: fused_seg<R, 8, MAGIC>(a, blocks, block, st, ev); break;
+        case 16: fused_seg<R, 16, MAGIC>(a, blocks, block, st, ev); break;
+        default: fused_seg<R, 32, MAGIC>(a, blocks, block, st, ev); break;
     }
 }
 
-hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st) {
-    if (precision == 64) fused_any<double, true>(a, blocks, block, st);
-    else if (use_magic(a, precision, block)) fused_any<float, true>(a, blocks, block, st);
-    else fused_any<float, false>(a, blocks, block, st);
+hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st, Ev ev) {
+    if (precision == 64) fused_any<double, true>(a, blocks, block, st, ev);
+    else if (use_magic(a, precision, block)) fused_any<float, true>(a, blocks, block, st, ev);
+    else fused_any<float, false>(a, blocks, block, st, ev);
     return hipGetLastError();
 }
 
-hipError_t launch_table(const Args &a, int precision, hipStream_t st) {
+hipError_t launch_table(const Args &a, int precision, hipStream_t st, Ev ev) {
     const long long ne = (long long)a.N * a.I;
     const int blocks = (int)((ne + 255) / 256 < 2048 ? (ne + 255) / 256 : 2048);
     if (precision == 64)
-        hipLaunchKernelGGL(k_table<double>, dim3(blocks), dim3(256), 0, st, a);
+        LAUNCH(k_table<double>, blocks, 256, 0, st, a);
     else
-        hipLaunchKernelGGL(k_table<float>, dim3(blocks), dim3(256), 0, st, a);
+        LAUNCH(k_table<float>, blocks, 256, 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, double *seg, int S,
-                        int n_opt, int G, const int *opt_orig, long long P, double spot,
-                        double *price, double *stderr_, double *grad, double *delta,
-                        hipStream_t st) {
-    const int Qm = (grad || delta) ? Q : 2 * n_opt;   // entries merged
-    hipLaunchKernelGGL(k_merge1, dim3((Qm + 255) / 256, S), dim3(256), 0, st, part, B_pay, B_grad,
-                       2 * n_opt, Q, Qm, S, seg);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // k_merge1 wrote rows of stride Qm; k_merge2 reads them with that stride.
-    const int T = n_opt + 1 + (grad ? G : 0);
-    hipLaunchKernelGGL(k_merge2, dim3((T + 255) / 256), dim3(256), 0, st, seg, S, Qm, n_opt,
-                       G, opt_orig, P, spot, price, stderr_, grad, delta);
+hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_opt, int G,
+                        const int *opt_orig, long long P, double spot, double *price, double *stderr_,
+                        double *grad, double *delta, hipStream_t st, Ev ev) {
+    const int T = n_opt + 1 + (grad ? G : 0);   // outputs, one wavefront each
+    const dim3 g((T + 3) / 4), b(256);
+    if (ev.start || ev.stop)
+        hipExtLaunchKernelGGL(k_merge, g, b, 0, st, ev.start, ev.stop, 0, part, B_pay, B_grad, Q, n_opt, G,
+                              opt_orig, P, spot, price, stderr_, grad, delta);
+    else
+        hipLaunchKernelGGL(k_merge, g, b, 0, st, part, B_pay, B_grad, Q, n_opt, G, opt_orig, P, spot, price,
+                           stderr_, grad, delta);
     return hipGetLastError();
 }
 
