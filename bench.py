@@ -76,6 +76,43 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes": a.numel() * 4}), flush=True)
 
 
+def other_workloads(lv, W, ctx, dev):
+    """The 64-option book and the 32-surface checkpointed batch at full size, each with
+    its autotuned launch shape: path-steps/s of price + grid adjoint (FP32)."""
+    import numpy as np
+    import torch
+    out = {}
+    wl = W.book_60x30()
+    s, b = wl.surface, wl.book
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device=dev)
+    kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, is_put=b.is_put, weights=b.weight, ctx=ctx,
+              autotune=True)
+    o = lv.price_and_grad_dev(sig, 100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps, wl.seed, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        lv.price_and_grad_dev(sig, 100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps, wl.seed, out=o, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 5
+    out[wl.name] = {"ms_per_step": ms, "value": wl.n_paths * wl.n_steps / (ms * 1e-3), "options": b.n,
+                    "adjoint": "stored, live paths"}
+    wl = W.surface_batch()
+    s, b = wl.surface, wl.book
+    sig = torch.tensor(np.stack([x.sigma for x in wl.surfaces]), dtype=torch.float64, device=dev)
+    kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, ctx=ctx, adjoint="checkpoint", ckpt_every=16,
+              autotune=True)
+    o = lv.price_and_grad_dev(sig, 100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps, wl.seed, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lv.price_and_grad_dev(sig, 100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps, wl.seed, out=o, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    n_s = len(wl.surfaces)
+    out[wl.name] = {"ms_per_step": ms, "value": n_s * wl.n_paths * wl.n_steps / (ms * 1e-3), "surfaces": n_s,
+                    "adjoint": "checkpoint every 16"}
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -204,6 +241,7 @@ def main():
             "ms_per_step": msd, "value": P * N / (msd * 1e-3),
             "max_bucket_diff_vs_live": float(np.abs(od[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
         result["variants"] = variants
+        result["workloads"] = other_workloads(lv, W, ctx, dev)
         result["accuracy"] = {
             "fp32_vs_fp64_gpu_price_abs": float(abs(price32.ravel()[0] - p64.ravel()[0])),
             "fp32_vs_fp64_gpu_max_bucket_err_rel_maxg": float(np.abs(grad32 - g64).max() / np.abs(g64).max()),

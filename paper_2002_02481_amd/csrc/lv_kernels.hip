@@ -443,8 +443,10 @@ __device__ __forceinline__ int fixed_point_bits(const Args &a, double qmax, int 
 // --------------------------------------------------------------------------
 // Forward kernel: price-only, or storing every state (split / stored adjoint).
 // --------------------------------------------------------------------------
+// FP32: at most 64 VGPRs, so that 8 waves fit per SIMD (the kernel is issue-bound)
 template <typename R, int AXIS, bool STORE>
-__global__ void __launch_bounds__(1024) k_fwd(Args a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
+k_fwd(Args a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int I = a.I, N = a.N, W = a.W, nW = (N + W - 1) / W;
