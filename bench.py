@@ -240,6 +240,13 @@ def main():
         variants["fp32_every_path_reverse"] = {
             "ms_per_step": msd, "value": P * N / (msd * 1e-3),
             "max_bucket_diff_vs_live": float(np.abs(od[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
+        # the host-buffer entry point: surface in, prices and grid out through PCIe (not `value`)
+        lv.price_and_grad(s, 100.0, strikes, mats, P, N, wl.seed, ctx=ctx, **shape)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            lv.price_and_grad(s, 100.0, strikes, mats, P, N, wl.seed, ctx=ctx, **shape)
+        msh = (time.perf_counter() - t0) * 1e3 / 5
+        variants["fp32_host_buffers_pcie"] = {"ms_per_step": msh, "value": P * N / (msh * 1e-3)}
         result["variants"] = variants
         result["workloads"] = other_workloads(lv, W, ctx, dev)
         result["accuracy"] = {
