@@ -172,8 +172,9 @@ int hist_window(const Plan &pl, const Shape &sh, size_t max_lds, int n_cu) {
     const size_t base = lds_adj(pl, sh, 0, n_cu);
     const size_t per_step = (size_t)(pl.I + 1) * sh.K * (pl.precision == 64 ? 8 : 4);
     long long wh = budget > base ? (long long)((budget - base) / per_step) / W * W : 0;
-    wh = std::max<long long>(W, std::min(wh, whole));
-    return (int)wh;
+    wh = std::min(wh, whole);
+    while (wh > W && lds_adj(pl, sh, (int)wh, n_cu) > budget) wh -= W;   // alignment padding
+    return (int)std::max<long long>(W, wh);
 }
 
 // Defaults from launch-shape sweeps on MI355X: 1024-lane blocks with 2 histogram
@@ -210,6 +211,9 @@ lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds,
     pl.K = sh.K;
     pl.W = table_window(pl, sh);
     pl.WH = hist_window(pl, sh, max_lds, n_cu);
+    if (lds_adj(pl, sh, pl.WH, n_cu) > max_lds)   // the window search keeps this; never launch past it
+        return fail(ctx, LV_ERR_UNSUPPORTED, "planner: histogram window of %d steps needs %zu bytes of LDS (limit %zu)",
+                    pl.WH, lds_adj(pl, sh, pl.WH, n_cu), max_lds);
     pl.CH = chunk_tiles(pl, sh, n_cu);
     pl.bpc = sh.bpc;
     pl.n_tiles = (int)((pl.P + pl.block - 1) / pl.block);
@@ -547,8 +551,9 @@ hipEvent_t take_event(lv_ctx *ctx) {
         ctx->event_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (cache writeback and invalidate) when recorded
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

@@ -630,14 +630,25 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
             // states are loaded at the start of a block, so loads have a whole block
             // of compute to arrive.
             R cur[RB], nxt[RB];
-            auto load_block = [&](int b, R(&y)[RB]) {
+            const R *Yp = Y + pc;   // this path's state at plane 0
 #pragma unroll
-                for (int k = 0; k < RB; ++k) {
-                    const int pl = min(max(b * RB + k - 1, 0), N - 1);
-                    y[k] = Y[(size_t)pl * P + pc];
+            for (int k = 0; k < RB; ++k) cur[k] = Yp[(size_t)min(max(btop * RB + k - 1, 0), N - 1) * P];
+            // Blocks below the top one read planes b RB - 1 .. b RB + RB - 2, which are
+            // below N - 1, and only plane -1 (block 0) needs the clamp; one pointer walks
+            // the planes, so no address is recomputed per load.  With fewer than RB
+            // steps the only block is the top one and the loads here are not used: the
+            // walk then stays on plane 0.
+            const size_t Ps = N >= RB ? P : 0;
+            auto load_block = [&](int b, R(&y)[RB]) {
+                const R *q = Yp + (size_t)max(b * RB - 1, 0) * Ps;
+                y[0] = *q;
+                q += b > 0 ? Ps : 0;
+#pragma unroll
+                for (int k = 1; k < RB; ++k) {
+                    y[k] = *q;
+                    q += Ps;
                 }
             };
-            load_block(btop, cur);
             for (int wi = nW - 1; wi >= 0; --wi) {
                 const int ws = wi * W, we = min(N, ws + W);
                 bool pending = false;
@@ -663,6 +674,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
                 auto group = [&](int n0, const R *y, auto full_tag) {
                     constexpr bool FULL = decltype(full_tag)::value;
                     const int wn0 = n0 - ws, hn0 = n0 - hbase;
+                    Acc *hrow = Hl + (hn0 + 3) * KI1;   // this lane's row of step n0 + 3
                     Look<R> L[4];
                     R cc[4], dsd[4], yup[4];
 #pragma unroll
@@ -690,8 +702,9 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
                             }
                             const R x = lam * cc[r];   // lam carries 2^F: x is the fixed-point term
                             lam = fma(x, dsd[r], lam);
-                            scatter<R>(a, Hl + (hn0 + r) * KI1, g64, n, L[r], x, qm, magic, inv_sc);
+                            scatter<R>(a, hrow, g64, n, L[r], x, qm, magic, inv_sc);
                         }
+                        hrow -= KI1;
                     }
                     if (FULL || n0 < N) y_next = (n0 == 0) ? (R)0 : y[0];
                 };

@@ -113,3 +113,25 @@ def test_tuning_candidates_are_valid_shapes():
 
 def test_copies_must_be_power_of_two():
     assert lv.check(**_req(), copies=3) == _lib.LV_ERR_ARG
+
+
+def test_planned_histogram_window_fits_lds():
+    """Every launch shape the checker accepts has a histogram window whose block fits the
+    CU's LDS (the planner refuses, with a 'planner:' message, if its window search
+    ever overshoots); shapes that cannot fit at all are refused by size."""
+    b = W.book64()
+    reqs = [_req(n_paths=1 << 19, n_steps=156),
+            dict(surface=W.book_surface(0), spot=100.0, strikes=b.strike, maturities=b.maturity,
+                 n_paths=1 << 20, n_steps=156, is_put=b.is_put, weights=b.weight)]
+    n_ok = 0
+    for req in reqs:
+        for prec, blocks in ((32, (128, 256, 512, 1024)), (64, (128, 256, 512))):
+            for block in blocks:
+                for k in (1, 2, 4, 8, 16):
+                    for win in (8, 16, 32, 64):
+                        st = lv.check(**req, precision=prec, block=block, copies=k, window=win)
+                        msg = _lib.load().lv_last_error(None).decode() if st else ""
+                        assert not msg.startswith("planner"), (prec, block, k, win, msg)
+                        assert st in (_lib.LV_OK, _lib.LV_ERR_UNSUPPORTED), (prec, block, k, win, st)
+                        n_ok += st == _lib.LV_OK
+    assert n_ok > 100
