@@ -264,6 +264,21 @@ def main():
         variants["fp32_every_path_reverse"] = {
             "ms_per_step": msd, "value": P * N / (msd * 1e-3),
             "max_bucket_diff_vs_live": float(np.abs(od[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
+        # bumping (Sec. III), the estimator the adjoint replaces: 2 I J forward pricings of
+        # bumped surfaces on the same paths, timed once after one untimed run
+        gb = torch.empty_like(sig)
+        bump = lambda: lv.bump_grad_dev(sig, 100.0, strikes, mats, P, N, wl.seed, spot_axis=s.spot_axis,
+                                        time_axis=s.time_axis, eps=1e-3, batch=512, out=gb, ctx=ctx, **shape)
+        bump()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bump()
+        torch.cuda.synchronize()
+        msb = (time.perf_counter() - t0) * 1e3
+        variants["fp32_bump_and_reprice"] = {
+            "ms_per_gradient": msb, "surfaces_priced": 2 * int(sig.numel()), "eps": 1e-3,
+            "slower_than_adjoint_step": msb / ms_per_step,
+            "max_bucket_diff_vs_adjoint": float(np.abs(gb.cpu().numpy() - grad32).max() / np.abs(grad32).max())}
         # the host-buffer entry point: surface in, prices and grid out through PCIe (not `value`)
         settle(lambda: lv.price_and_grad(s, 100.0, strikes, mats, P, N, wl.seed, ctx=ctx, **shape), 5)
         t0 = time.perf_counter()

@@ -171,6 +171,23 @@ lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf
                                 const lv_opts *opts, double *prices_dev, double *std_errs_dev,
                                 double *grads_dev, double *deltas_dev);
 
+/* Bump-and-reprice: the vol-grid gradient by the finite differences the adjoint
+ * replaces (arXiv 2002.02481, Sec. III: one simulation at p + eps/2, one at
+ * p - eps/2, the difference over eps), for comparison with it.  For every node
+ * (i, j), the book is priced on sigma with sigma_ij moved by +eps/2 and by -eps/2,
+ * forward only, on the same Philox paths as the adjoint (common random numbers),
+ * and grad_dev[i*J + j] = sum_k weight_k (price_k(+) - price_k(-)) / eps.
+ * sigma_dev: [I*J] FP64 device; grad_dev: [I*J] FP64 device, caller-owned.  eps:
+ * absolute vol bump, finite and > 0 (a node with sigma_ij <= eps/2 is priced with
+ * a non-positive vol: the caller picks eps).  2 I J surfaces are priced, at most
+ * `batch` nodes (2 batch surfaces) per batch (0 = 256), through the same kernels as
+ * lv_price_and_grad_dev with adjoint NONE; opts->adjoint is ignored.  Device
+ * workspace: (2 batch (I J + 2 n_opt) + n_opt) doubles, held by the context.
+ * Asynchronous on the context's stream; LV_ERR_ARG for a bad eps or batch. */
+lv_status lv_bump_grad_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                           const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                           const lv_opts *opts, double eps, int32_t batch, double *grad_dev);
+
 /* Bytes of the path-state buffer the split calls use: n_steps planes of
  * n_paths values (float for precision 32, double for 64), plane n holding
  * y_{n+1} of every path (path index contiguous). */

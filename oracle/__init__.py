@@ -14,6 +14,7 @@ vol node (Sec. III, IV-C).
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import os
 import subprocess
 from typing import Dict, Optional, Sequence, Tuple
@@ -169,6 +170,31 @@ class Oracle:
         stderr = np.sqrt(np.maximum(var, 0.0) / P)
         grad = s["sum_grad"] / P if want_grad else None
         return dict(price=price, stderr=stderr, grad=grad, delta=s["sum_lam0"] / P / spot)
+
+
+    def bump_grad(self, surface, book, n_paths: int, n_steps: int, seed: int = 0, eps: float = 1e-4,
+                  nodes: Optional[Sequence[Tuple[int, int]]] = None, n_threads: int = 0,
+                  spot: float = 100.0) -> np.ndarray:
+        """Finite-difference ("bumping", Sec. III) derivative of the weighted book value
+        with respect to the listed nodes (all when None): the book priced on the same
+        paths with sigma_ij + eps/2 and with sigma_ij - eps/2, the difference over eps.
+        Returns [len(nodes)] in the order given."""
+        I, J = surface.sigma.shape
+        if nodes is None:
+            nodes = [(i, j) for i in range(I) for j in range(J)]
+        w = np.asarray(book.weight, dtype=np.float64)
+        out = np.zeros(len(nodes))
+        for q, (i, j) in enumerate(nodes):
+            vals = []
+            for h in (0.5 * eps, -0.5 * eps):
+                sig = np.array(surface.sigma, dtype=np.float64, copy=True)
+                sig[i, j] += h
+                bumped = dataclasses.replace(surface, sigma=sig)
+                r = self.price_and_grad(bumped, book, n_paths, n_steps, seed, n_threads, spot,
+                                        want_grad=False)
+                vals.append(float(np.dot(w, r["price"])))
+            out[q] = (vals[0] - vals[1]) / eps
+        return out
 
 
 _default: Optional[Oracle] = None

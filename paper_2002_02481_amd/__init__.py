@@ -21,7 +21,8 @@ from . import _lib
 from ._lib import ADJOINT, LVError, lv_axis, lv_book, lv_grid, lv_opts, lv_run_info
 
 __all__ = ["Context", "LVError", "price_and_grad", "price_and_grad_batch", "price_and_grad_dev",
-           "forward_dev", "backward_dev", "states_bytes", "LVPrice", "check", "default_context"]
+           "forward_dev", "backward_dev", "states_bytes", "LVPrice", "check", "default_context",
+           "bump_grad_dev", "per_option_grads_dev"]
 
 
 def _lib_handle():
@@ -276,6 +277,50 @@ def price_and_grad_dev(sigmas, spot, strikes, maturities, n_paths, n_steps, seed
         int(n_steps), int(seed), C.byref(o), _ptr(prices), _ptr(stderrs), _ptr(grads), _ptr(deltas))
     _check_status(st, ctx.h)
     return prices, stderrs, grads, deltas
+
+
+def bump_grad_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed=0, *, spot_axis, time_axis,
+                  is_put=None, weights=None, eps=1e-4, batch=0, out=None, ctx: Optional[Context] = None,
+                  **opts):
+    """Bump-and-reprice gradient [I, J] of sum_k w_k price_k by central differences of
+    width eps on every node (same paths as the adjoint), for comparison with it.
+    sigma is a CUDA float64 tensor [I, J]; runs on torch's current stream."""
+    import torch
+    ctx = ctx or default_context(sigma.device.index or 0)
+    ctx.use_torch_stream()
+    assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
+    grid = make_grid(spot_axis, time_axis)
+    book = _Book(strikes, maturities, is_put, weights)
+    o = make_opts(**opts)
+    grad = out if out is not None else torch.empty(sigma.shape[-2:], dtype=torch.float64, device=sigma.device)
+    st = ctx.lib.lv_bump_grad_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),
+                                  int(n_paths), int(n_steps), int(seed), C.byref(o), float(eps),
+                                  int(batch), _ptr(grad))
+    _check_status(st, ctx.h)
+    return grad
+
+
+def per_option_grads_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed=0, *, spot_axis,
+                         time_axis, is_put=None, precision=32, ctx: Optional[Context] = None):
+    """Per-option vol-grid gradients from one simulation: the states are stored once by
+    the split forward, then the reverse runs once per option with a one-hot cotangent.
+    Returns (prices [n], std_errs [n], grads [n, I, J], deltas [n]) CUDA tensors."""
+    import torch
+    price, stderr, states = forward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed,
+                                        spot_axis=spot_axis, time_axis=time_axis, is_put=is_put,
+                                        precision=precision, ctx=ctx)
+    n = price.numel()
+    grads = torch.empty((n,) + tuple(sigma.shape), dtype=torch.float64, device=sigma.device)
+    deltas = torch.empty(n, dtype=torch.float64, device=sigma.device)
+    for k in range(n):
+        cot = torch.zeros(n, dtype=torch.float64, device=sigma.device)
+        cot[k] = 1.0
+        g, d = backward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, states, cot,
+                            spot_axis=spot_axis, time_axis=time_axis, is_put=is_put,
+                            precision=precision, want_delta=True, ctx=ctx)
+        grads[k] = g
+        deltas[k] = d[0]
+    return price, stderr, grads, deltas
 
 
 def states_bytes(precision: int, n_paths: int, n_steps: int) -> int:

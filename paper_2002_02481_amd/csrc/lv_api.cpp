@@ -58,7 +58,7 @@ struct lv_ctx {
     int n_cu = 256;
     size_t max_lds = 65536;
     std::string err = "no error";
-    Buf planbuf, part, states, ckpt, sig_stage, out_stage, gtab;
+    Buf planbuf, part, states, ckpt, sig_stage, out_stage, gtab, bump;
     std::vector<char> plan_bytes;     // what planbuf holds
     lv_run_info info{};
     int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
@@ -852,7 +852,7 @@ void lv_destroy(lv_ctx *ctx) {
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&ctx->planbuf, &ctx->part, &ctx->states, &ctx->ckpt,
-                   &ctx->sig_stage, &ctx->out_stage, &ctx->gtab};
+                   &ctx->sig_stage, &ctx->out_stage, &ctx->gtab, &ctx->bump};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -892,6 +892,38 @@ lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf
     HIPCHECK(ctx, hipSetDevice(ctx->device));
     return run_dev(ctx, pl, n_surf, sigmas_dev, adjoint, opts && opts->use_graph, prices_dev,
                    std_errs_dev, grads_dev, deltas_dev);
+}
+
+lv_status lv_bump_grad_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                           const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                           const lv_opts *opts, double eps, int32_t batch, double *grad_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigma_dev || !grad_dev) return fail(ctx, LV_ERR_ARG, "sigma and grad are required");
+    if (!(std::isfinite(eps) && eps > 0.0)) return fail(ctx, LV_ERR_ARG, "eps must be finite and > 0");
+    if (batch < 0) return fail(ctx, LV_ERR_ARG, "batch must be >= 0");
+    lv_opts o = opts ? *opts : lv_opts{};
+    o.adjoint = LV_ADJ_NONE;   // forward pricing only
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, 1, nullptr, spot, book, n_paths, n_steps, seed, &o, ctx->n_cu,
+                               ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    const int G = pl.G, nb = std::min(G, batch > 0 ? (int)batch : 256);   // nodes per batch
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    const size_t n_sig = (size_t)2 * nb * G, n_pr = (size_t)2 * nb * pl.n_opt;
+    if ((s = ensure(ctx, ctx->bump, (n_sig + 2 * n_pr + pl.n_opt) * 8)) != LV_OK) return s;
+    double *sig_b = (double *)ctx->bump.p, *pr = sig_b + n_sig, *se = pr + n_pr, *w = se + n_pr;
+    hipStream_t st = ctx->stream();
+    HIPCHECK(ctx, hipMemcpyAsync(w, pl.weight.data(), pl.n_opt * 8, hipMemcpyHostToDevice, st));
+    for (int m0 = 0; m0 < G; m0 += nb) {
+        const int mc = std::min(nb, G - m0);
+        hipError_t e = lvk::launch_bump(sigma_dev, G, m0, mc, eps, sig_b, st);
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        if ((s = run_dev(ctx, pl, 2 * mc, sig_b, false, o.use_graph != 0, pr, se, nullptr, nullptr)) != LV_OK)
+            return s;
+        e = lvk::launch_fd(pr, pl.n_opt, w, m0, mc, eps, grad_dev, st);
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    return LV_OK;
 }
 
 lv_status lv_price_and_grad_batch(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,

@@ -79,6 +79,11 @@ hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block
 hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_opt, int G,
                         const int *opt_orig, long long P, double spot, double *price, double *stderr_,
                         double *grad, double *delta, hipStream_t st, Ev ev = {});
+// Bump-and-reprice: 2 mc bumped copies of sigma [G] (node m0 + s at +-eps/2) into
+// out [2 mc][G]; then grad[m0 + s] = sum_k weight_k (price[2s][k] - price[2s+1][k]) / eps.
+hipError_t launch_bump(const double *sigma, int G, int m0, int mc, double eps, double *out, hipStream_t st);
+hipError_t launch_fd(const double *prices, int n_opt, const double *weight, int m0, int mc, double eps,
+                     double *grad, hipStream_t st);
 hipError_t launch_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
                                unsigned long long p0, long long n_paths, uint32_t *out,
                                hipStream_t st);

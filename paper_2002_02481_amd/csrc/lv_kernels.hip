@@ -982,6 +982,30 @@ __global__ void k_merge(const double *part, int B_pay, int B_grad, int Q, int n_
 // --------------------------------------------------------------------------
 // Test-support kernels
 // --------------------------------------------------------------------------
+// --------------------------------------------------------------------------
+// Bump-and-reprice (the finite-difference estimator the adjoint replaces, Sec. III):
+// surfaces 2s and 2s+1 of a batch are sigma with node m0 + s moved by +eps/2 and
+// -eps/2; after they are priced on the same paths, the node's derivative is the
+// weighted price difference over eps.
+// --------------------------------------------------------------------------
+__global__ void k_bump(const double *sigma, int G, int m0, int mc, double eps, double *out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2LL * mc * G) return;
+    const int s = (int)(e / G), g = (int)(e - (long long)s * G);
+    const double v = sigma[g];
+    out[e] = g == m0 + s / 2 ? v + ((s & 1) ? -0.5 * eps : 0.5 * eps) : v;
+}
+
+__global__ void k_fd(const double *prices, int n_opt, const double *weight, int m0, int mc, double eps,
+                     double *grad) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= mc) return;
+    const double *up = prices + (size_t)(2 * s) * n_opt, *dn = up + n_opt;
+    double acc = 0.0;
+    for (int k = 0; k < n_opt; ++k) acc += weight[k] * (up[k] - dn[k]);
+    grad[m0 + s] = acc / eps;
+}
+
 __global__ void k_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
                                unsigned long long p0, long long n_paths, uint32_t *out) {
     const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -1136,6 +1160,18 @@ hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_
     else
         hipLaunchKernelGGL(k_merge, g, b, 0, st, part, B_pay, B_grad, Q, n_opt, G, opt_orig, P, spot, price,
                            stderr_, grad, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump(const double *sigma, int G, int m0, int mc, double eps, double *out, hipStream_t st) {
+    const long long n = 2LL * mc * G;
+    hipLaunchKernelGGL(k_bump, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sigma, G, m0, mc, eps, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd(const double *prices, int n_opt, const double *weight, int m0, int mc, double eps,
+                     double *grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_fd, dim3((mc + 255) / 256), dim3(256), 0, st, prices, n_opt, weight, m0, mc, eps, grad);
     return hipGetLastError();
 }
 

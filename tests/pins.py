@@ -356,18 +356,8 @@ def pin_two_steps(o, n_paths=1 << 17, n_batches=32):
 # --------------------------------------------------------------------------
 def crn_fd_grad(o, surface, book, n_paths, n_steps, seed, eps=1e-5):
     """Central bump of every node, (value(p+eps/2) - value(p-eps/2)) / eps, on the same
-    random streams, of the weighted book value."""
-    g = np.zeros_like(surface.sigma)
-    for i in range(surface.sigma.shape[0]):
-        for j in range(surface.sigma.shape[1]):
-            vals = []
-            for sgn in (+0.5, -0.5):
-                sig = surface.sigma.copy(); sig[i, j] += sgn * eps
-                r = o.price_and_grad(W.Surface(surface.spot_axis, surface.time_axis, sig),
-                                     book, n_paths, n_steps, seed, want_grad=False)
-                vals.append(float(np.dot(book.weight, r["price"])))
-            g[i, j] = (vals[0] - vals[1]) / eps
-    return g
+    random streams, of the weighted book value (the oracle's bumping estimator)."""
+    return o.bump_grad(surface, book, n_paths, n_steps, seed, eps).reshape(surface.sigma.shape)
 
 
 def pin_adjoint_fd(o):

@@ -313,6 +313,70 @@ def batch_stderr(orc, surface, book, n_paths, n_steps, seed, n_batches=32):
     return gs.std(axis=0, ddof=1) / math.sqrt(n_batches)
 
 
+def test_per_option_grads_sum_to_book(lv, ctx):
+    """Per-option grids (one stored forward, one reverse per option with a one-hot
+    cotangent) equal the fused call's grid with that option's weight alone, and add up,
+    with the book's weights, to the grid of the weighted book (FP64)."""
+    import torch
+    s = W.small_surface()
+    book = W.Book([0, 1, 0], [100.0, 105.0, 92.0], [1.0, 0.5, 0.75], [1.0, 2.5, -0.7])
+    P, N = 8192, 52
+    say(f"  per-option grids: {s.sigma.shape} P={P} N={N}")
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device="cuda")
+    pr, se, grads, deltas = lv.per_option_grads_dev(sig, 100.0, book.strike, book.maturity, P, N, 0,
+                                                    spot_axis=s.spot_axis, time_axis=s.time_axis,
+                                                    is_put=book.is_put, precision=64, ctx=ctx)
+    grads, deltas = grads.cpu().numpy(), deltas.cpu().numpy()
+    fused = gpu_run(lv, ctx, s, book, P, N, precision=64)
+    scale = np.abs(fused["grad"]).max()
+    summed = np.tensordot(book.weight, grads, axes=1)
+    assert np.abs(summed - fused["grad"]).max() < 1e-10 * scale
+    assert abs(float(np.dot(book.weight, deltas)) - float(np.ravel(fused["delta"])[0])) < 1e-10
+    np.testing.assert_allclose(pr.cpu().numpy(), fused["price"], rtol=1e-12, atol=0)
+    for k in range(book.n):
+        w = np.zeros(book.n)
+        w[k] = 1.0
+        one = gpu_run(lv, ctx, s, W.Book(book.is_put, book.strike, book.maturity, w), P, N, precision=64)
+        sk = max(np.abs(one["grad"]).max(), 1e-300)
+        assert np.abs(grads[k] - one["grad"]).max() < 1e-10 * sk, k
+
+
+def test_bump_and_reprice(lv, ctx, orc):
+    """The bumping estimator (Sec. III) on the GPU: FP64, it equals the oracle's at sampled
+    nodes on the same paths and agrees with the adjoint grid to the finite-difference
+    error (paths whose payoff kink or grid cell changes between the two bumps give an
+    O(eps) term: at eps 1e-4 the oracle's own bumping is 5e-5 max|g| off its adjoint on
+    this workload, at 1e-5 2e-7); batches of 64 nodes leave a ragged last batch
+    (21 x 13 = 273 nodes)."""
+    import torch
+    s = W.small_surface()
+    book = W.call(100.0, 1.0)
+    P, N, eps = 16384, 52, 1e-5
+    say(f"  bump-and-reprice: {s.sigma.shape} P={P} N={N} eps={eps}")
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device="cuda")
+    kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, is_put=book.is_put, weights=book.weight, ctx=ctx)
+    fd = lv.bump_grad_dev(sig, 100.0, book.strike, book.maturity, P, N, 0, eps=eps, batch=64, precision=64,
+                          **kw).cpu().numpy()
+    ad = gpu_run(lv, ctx, s, book, P, N, precision=64)["grad"]
+    scale = np.abs(ad).max()
+    err = np.abs(fd - ad).max()
+    say(f"  FP64 bump vs adjoint: {err / scale:.3g} max|g|")
+    assert err < 1e-5 * scale
+    order = np.argsort(-np.abs(ad).ravel())
+    nodes = [divmod(int(k), ad.shape[1]) for k in list(order[:4]) + [int(order[40]), int(order[-1])]]
+    ref = orc.bump_grad(s, book, P, N, 0, eps, nodes)
+    got = np.array([fd[i, j] for i, j in nodes])
+    say(f"  FP64 bump vs oracle bump: {np.abs(got - ref).max() / scale:.3g} max|g|")
+    assert np.abs(got - ref).max() < 1e-8 * scale
+    # FP32 stepping needs a wider bump: its rounding noise in a price difference is
+    # divided by eps
+    fd32 = lv.bump_grad_dev(sig, 100.0, book.strike, book.maturity, P, N, 0, eps=1e-3, precision=32,
+                            **kw).cpu().numpy()
+    err32 = np.abs(fd32 - ad).max() / scale
+    say(f"  FP32 bump (eps 1e-3) vs FP64 adjoint: {err32:.3g} max|g|")
+    assert err32 < 5e-3
+
+
 def test_full_size_single_call_60x30(lv, ctx, orc):
     """The benchmark workload at full size (2^19 paths, 156 steps, 60 x 30 grid) in the
     benchmark's launch configuration.  FP64 kernels: the tight bar.  FP32 kernels:
