@@ -124,7 +124,15 @@ typedef struct {
     int32_t profile_kinds;  /* with profile: bit (1 << LV_K_*) set = time that kernel kind; 0 = all.
                                A timed dispatch waits for its timestamp (several microseconds),
                                so timing only the kernel of interest keeps the others' pace */
+    int32_t scheme;         /* LV_SCHEME_LOG_EULER (default): the explicit Euler step on
+                               y = ln(X/X0) with the Ito drift -sigma^2/2; LV_SCHEME_EULER_X: the
+                               explicit Euler step on X itself, X += sigma(X, t) X sqrt(dt) Z, as
+                               Sec. IV-A narrates the scheme (stored and price-only adjoint modes;
+                               LV_ERR_UNSUPPORTED with LV_ADJ_CHECKPOINT).  The split calls
+                               lv_forward_dev / lv_backward_dev step log-Euler. */
 } lv_opts;
+
+enum { LV_SCHEME_LOG_EULER = 0, LV_SCHEME_EULER_X = 1 };
 
 /* Create a context on HIP device `device` that launches on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  The context owns a device

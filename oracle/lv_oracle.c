@@ -12,7 +12,8 @@
  * What it computes, in the paper's terms:
  *   - the model dX/X = sigma(X,t) dW, no drift (Sec. IV-A, the SDE);
  *   - an explicit Euler scheme (Sec. IV-A), taken on y = ln(X/X0) with the Ito
- *     drift -sigma^2/2, sigma read at the left point of each step;
+ *     drift -sigma^2/2, sigma read at the left point of each step; or (scheme 1)
+ *     the explicit Euler step on X itself, as the paper narrates the scheme;
  *   - sigma(S,t) by bilinear interpolation of a grid of nodes {(i dx, j dt)}
  *     (Sec. IV-A, the grid; Sec. IV-D, bilinear interpolation), flat outside;
  *   - Gaussian increments from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
@@ -122,6 +123,7 @@ typedef struct {
     const double *strike, *maturity, *weight;
     int32_t n_steps;
     uint64_t seed;
+    int32_t scheme;              /* 0: log-Euler on y = ln(X/X0); 1: Euler on X */
     /* derived */
     double dt, sqrt_dt;
     int32_t *tap_step;           /* [n_opt] step index of each maturity */
@@ -144,6 +146,7 @@ static int lvo_setup(lvo_problem *pb)
     if (pb->spot_kind != 0 && pb->spot_kind != 1) return lvo_fail("unknown axis kind");
     if (!(pb->spot > 0.0)) return lvo_fail("spot must be positive");
     if (pb->n_opt < 1 || pb->n_steps < 1) return lvo_fail("need n_opt >= 1 and n_steps >= 1");
+    if (pb->scheme != 0 && pb->scheme != 1) return lvo_fail("unknown scheme");
     for (int64_t q = 0; q < (int64_t)pb->n_spot * pb->n_time; ++q)
         if (!(isfinite(pb->sigma[q]) && pb->sigma[q] > 0.0)) return lvo_fail("sigma nodes must be finite and positive");
     double tmax = 0.0;
@@ -313,6 +316,58 @@ static void lvo_one_path(const lvo_problem *pb, uint64_t p, lvo_work *w,
     *lam0 = lam;
 }
 
+/* The explicit Euler step on X itself (scheme 1: the step as Sec. IV-A narrates
+ * it, today's price plus a Gaussian term whose scale is sigma(X, t) X):
+ *   X_{n+1} = X_n + sigma(X_n, t_n) X_n sqrt(dt) Z_n,
+ * and its reverse sweep, with lambda the adjoint of X:
+ *   d X_{n+1} / d sigma_n = X_n sqrt(dt) Z_n,
+ *   d X_{n+1} / d X_n     = 1 + sqrt(dt) Z_n (sigma_n + X_n d sigma / d X),
+ *   d payoff / d X        = 1{X > K} (call), -1{X < K} (put).
+ * w->y holds X here.  lam_hist and *lam0 report the adjoint of ln X_n (lambda X_n),
+ * the quantity the log scheme reports, so that sums and deltas read the same. */
+static void lvo_one_path_euler_x(const lvo_problem *pb, uint64_t p, lvo_work *w,
+                                 double *payoffs, double *grad, double *lam0, double *lam_hist)
+{
+    int32_t N = pb->n_steps;
+    double dt = pb->dt, sdt = pb->sqrt_dt;
+    double *X = w->y;
+    X[0] = pb->spot;
+    for (int32_t n = 0; n < N; ++n) {
+        lvo_eval(pb, X[n], n * dt, &w->iv[n]);
+        w->z[n] = lvo_normal(pb->seed, p, n);
+        X[n + 1] = X[n] + w->iv[n].sigma * X[n] * sdt * w->z[n];
+    }
+    for (int k = 0; k < pb->n_opt; ++k) {
+        double x = X[pb->tap_step[k]], K = pb->strike[k];
+        payoffs[k] = pb->is_put[k] ? (K > x ? K - x : 0.0) : (x > K ? x - K : 0.0);
+    }
+    double lam = 0.0;
+    int32_t J = pb->n_time;
+    for (int32_t n = N; n >= 1; --n) {
+        for (int k = 0; k < pb->n_opt; ++k)
+            if (pb->tap_step[k] == n) {
+                double wk = pb->weight ? pb->weight[k] : 1.0, K = pb->strike[k];
+                if (pb->is_put[k]) lam -= K > X[n] ? wk : 0.0;
+                else lam += X[n] > K ? wk : 0.0;
+            }
+        if (lam_hist) lam_hist[n] = lam * X[n];
+        const lvo_interp *iv = &w->iv[n - 1];
+        double c = X[n - 1] * sdt * w->z[n - 1];     /* d X_n / d s_{n-1} */
+        if (grad) {
+            /* nodes (i,j), (i+1,j), (i,j+1), (i+1,j+1) of the step's cell */
+            int64_t q00 = (int64_t)iv->i * J + iv->j;
+            grad[q00] += lam * c * iv->w[0];
+            grad[q00 + J] += lam * c * iv->w[1];
+            grad[q00 + 1] += lam * c * iv->w[2];
+            grad[q00 + J + 1] += lam * c * iv->w[3];
+        }
+        /* X d sigma / d X = d sigma / d ln X */
+        lam = lam * (1.0 + sdt * w->z[n - 1] * (iv->sigma + iv->dsigma_dy));
+    }
+    if (lam_hist) lam_hist[0] = lam * X[0];
+    *lam0 = lam * X[0];
+}
+
 /* ------------------------------------------------------------------------- */
 /* Chunked, threaded accumulation over path ranges                           */
 /* ------------------------------------------------------------------------- */
@@ -351,7 +406,8 @@ static void *lvo_worker(void *arg)
         double *grad = job->want_grad ? out + 2 * n_opt + 1 : NULL;
         for (int64_t p = job->chunks[c].begin; p < job->chunks[c].end; ++p) {
             double lam0;
-            lvo_one_path(pb, (uint64_t)p, &w, pay, grad, &lam0, NULL);
+            if (pb->scheme == 1) lvo_one_path_euler_x(pb, (uint64_t)p, &w, pay, grad, &lam0, NULL);
+            else lvo_one_path(pb, (uint64_t)p, &w, pay, grad, &lam0, NULL);
             for (int k = 0; k < n_opt; ++k) {
                 out[k] += pay[k];
                 out[n_opt + k] += pay[k] * pay[k];
@@ -388,10 +444,11 @@ int lvo_accumulate(int32_t n_spot, int32_t spot_kind, double spot_lo, double spo
                    double spot, int32_t n_opt, const int32_t *is_put, const double *strike,
                    const double *maturity, const double *weight, int32_t n_steps, uint64_t seed,
                    int64_t n_ranges, const int64_t *ranges, int32_t n_threads,
-                   double *sum_pay, double *sum_pay2, double *sum_grad, double *sum_lam0)
+                   double *sum_pay, double *sum_pay2, double *sum_grad, double *sum_lam0,
+                   int32_t scheme)
 {
     lvo_problem pb = {n_spot, spot_kind, spot_lo, spot_hi, n_time, time_lo, time_hi, sigma,
-                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, 0, 0, NULL};
+                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, scheme, 0, 0, NULL};
     if (lvo_setup(&pb) != 0) return -1;
 
     int64_t n_chunks = 0;
@@ -450,25 +507,27 @@ int lvo_accumulate(int32_t n_spot, int32_t spot_kind, double spot_lo, double spo
 
 /*
  * Everything about a single path p, for inspection:
- *   y[N+1], z[N], sigma[N], dsdy[N], lam[N+1] (lambda after the seeds of step n;
- *   lam[0] = d/dy_0), payoff[n_opt], grad[I*J] (this path's contribution).
+ *   y[N+1] (ln(X/X0) for scheme 0, X for scheme 1), z[N], sigma[N], dsdy[N],
+ *   lam[N+1] (the adjoint of ln X_n after the seeds of step n; lam[0] = d/dy_0),
+ *   payoff[n_opt], grad[I*J] (this path's contribution).
  */
 int lvo_path(int32_t n_spot, int32_t spot_kind, double spot_lo, double spot_hi,
              int32_t n_time, double time_lo, double time_hi, const double *sigma,
              double spot, int32_t n_opt, const int32_t *is_put, const double *strike,
              const double *maturity, const double *weight, int32_t n_steps, uint64_t seed,
              int64_t p, double *y, double *z, double *sig, double *dsdy, double *lam,
-             double *payoff, double *grad)
+             double *payoff, double *grad, int32_t scheme)
 {
     lvo_problem pb = {n_spot, spot_kind, spot_lo, spot_hi, n_time, time_lo, time_hi, sigma,
-                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, 0, 0, NULL};
+                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, scheme, 0, 0, NULL};
     if (lvo_setup(&pb) != 0) return -1;
     lvo_work w;
     lvo_work_alloc(&w, n_steps);
     int64_t G = (int64_t)n_spot * n_time;
     memset(grad, 0, sizeof(double) * G);
     double lam0;
-    lvo_one_path(&pb, (uint64_t)p, &w, payoff, grad, &lam0, lam);
+    if (pb.scheme == 1) lvo_one_path_euler_x(&pb, (uint64_t)p, &w, payoff, grad, &lam0, lam);
+    else lvo_one_path(&pb, (uint64_t)p, &w, payoff, grad, &lam0, lam);
     memcpy(y, w.y, sizeof(double) * (n_steps + 1));
     memcpy(z, w.z, sizeof(double) * n_steps);
     for (int32_t n = 0; n < n_steps; ++n) {

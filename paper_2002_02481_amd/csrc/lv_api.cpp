@@ -43,6 +43,7 @@ struct Plan {
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;   // profile: kinds to time (bits)
     int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, bpc = 2, CH = 1;
     int dense = 0;   // reverse kernel sweeps every path (not only those with a nonzero adjoint)
+    int scheme = 0;  // 0: Euler on ln X; 1: Euler on X
     int fblock = 256, fblocks = 0, f_n_tiles = 0, fbpc = 2;
     int G = 0, Q = 0;
     Shape user{0, 0, 0, 0, 0, 0};   // caller-fixed shape fields (0 = free)
@@ -305,6 +306,10 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     if (o.precision != 32 && o.precision != 64) return fail(ctx, LV_ERR_ARG, "precision must be 32 or 64");
     if (o.adjoint < 0 || o.adjoint > 3) return fail(ctx, LV_ERR_ARG, "unknown adjoint mode %d", o.adjoint);
     if (o.adjoint == LV_ADJ_DEFAULT) o.adjoint = LV_ADJ_STORED;
+    if (o.scheme != LV_SCHEME_LOG_EULER && o.scheme != LV_SCHEME_EULER_X)
+        return fail(ctx, LV_ERR_ARG, "unknown scheme %d", o.scheme);
+    if (o.scheme == LV_SCHEME_EULER_X && o.adjoint == LV_ADJ_CHECKPOINT)
+        return fail(ctx, LV_ERR_UNSUPPORTED, "the Euler step on X runs with the stored or no adjoint");
     if (o.ckpt_every == 0) o.ckpt_every = 16;
     if (o.ckpt_every != 8 && o.ckpt_every != 16 && o.ckpt_every != 32)
         return fail(ctx, LV_ERR_ARG, "ckpt_every must be 8, 16 or 32");
@@ -338,6 +343,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     pl.seg = o.ckpt_every;
     pl.profile = o.profile ? (o.profile_kinds ? o.profile_kinds : (1 << LV_K_COUNT) - 1) : 0;
     pl.dense = o.dense_adjoint ? 1 : 0;
+    pl.scheme = o.scheme;
     pl.G = (int)G;
     pl.Q = 2 * pl.n_opt + 1 + pl.G;
 
@@ -517,6 +523,7 @@ lvk::Args make_args(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *
     a.K = pl.K;
     a.CH = pl.CH;
     a.dense = pl.dense;
+    a.scheme = pl.scheme;
     a.seg = pl.seg;
     return a;
 }
@@ -653,7 +660,8 @@ std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf
     char buf[128];
     snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I,
              pl.J, pl.N, pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
-             pl.blocks, pl.W, pl.WH, pl.K, pl.CH, pl.dense, pl.fblock, pl.fblocks, pl.spot, pl.dt, n_surf);
+             pl.blocks, pl.W, pl.WH, pl.K, pl.CH, pl.dense * 2 + pl.scheme, pl.fblock, pl.fblocks, pl.spot, pl.dt,
+             n_surf);
     k += buf;
     k += adjoint ? "A|" : "F|";
     for (int i = 0; i < n_ptrs; ++i) {
@@ -668,7 +676,7 @@ std::string tune_key(const Plan &pl, bool adjoint) {
     snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N,
              pl.axis, pl.P, pl.precision, adjoint ? pl.adjoint : LV_ADJ_NONE, pl.seg, pl.n_opt,
              pl.n_taps, pl.user.block, pl.user.K, pl.user.W, pl.user.bpc, pl.user.fblock,
-             pl.user.fbpc, (int)pl.profile, pl.dense);
+             pl.user.fbpc, (int)pl.profile, pl.dense * 2 + pl.scheme);
     return buf;
 }
 

@@ -47,6 +47,7 @@ struct Args {
     int CH;                     // reverse kernel: path tiles per live-path list
     int dense;                  // reverse kernel: sweep every path, not only live ones
     int seg;                    // checkpoint segment (steps)
+    int scheme;                 // 0: Euler on y = ln(X/X0); 1: Euler on X (stored states hold X)
 };
 
 enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };

@@ -89,6 +89,7 @@ struct Math<float> {
         return __builtin_amdgcn_exp2f(y * 1.44269504f);
     }
     __device__ static __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static __forceinline__ float lg(float x) { return __builtin_amdgcn_logf(x) * 0.693147181f; }
     // (q0, q1) = (rn(x) - rn(xf), rn(xf)).  For |x|, |xf| <= 2^22 (MAGIC_MAX) adding
     // 1.5 * 2^23 rounds to an integer (nearest, ties to even) held in the low
     // mantissa bits, so bit patterns differ by the integers themselves; larger
@@ -125,6 +126,7 @@ struct Math<double> {
     }
     __device__ static __forceinline__ double ex(double y) { return exp(y); }
     __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
+    __device__ static __forceinline__ double lg(double x) { return log(x); }
     // as for float with 1.5 * 2^52; the FP64 range is capped at 2^51, so always exact
     static constexpr double MAGIC_MAX = 2251799813685248.0;
     __device__ static __forceinline__ void to_acc2(double x, double xf, bool, Acc &q0, Acc &q1) {
@@ -295,17 +297,12 @@ struct Look {
     bool in;   // strictly inside the spot range (slope is zero outside)
 };
 
-template <typename R, int AXIS>
-__device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off, R amax, R spot) {
+// Lookup at axis coordinate x (S on a linear axis, ln S on a log one) with offset
+// a_off: a = x / du + a_off is the grid coordinate.
+template <typename R>
+__device__ __forceinline__ Look<R> lookup_at(R x, const R *trow, R inv_du, R a_off, R amax) {
     Look<R> L;
-    R x;
-    if (AXIS == 0) {
-        L.S = spot * Math<R>::ex(y);
-        x = L.S;
-    } else {
-        L.S = 0;
-        x = y;
-    }
+    L.S = 0;
     const R a = fma(x, inv_du, a_off);
     L.in = (a > (R)0) && (a < amax);
     const R ac = clamp_to(a, amax);
@@ -319,12 +316,37 @@ __device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off,
     return L;
 }
 
+// Lookup at log-spot state y = ln(S / spot) (L.S = S on a linear axis).
+template <typename R, int AXIS>
+__device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off, R amax, R spot) {
+    if (AXIS == 0) {
+        const R S = spot * Math<R>::ex(y);
+        Look<R> L = lookup_at<R>(S, trow, inv_du, a_off, amax);
+        L.S = S;
+        return L;
+    }
+    return lookup_at<R>(y, trow, inv_du, a_off, amax);
+}
+
+// Lookup at the state of either scheme: y = ln(X / spot) (EX false) or X itself (EX
+// true; L.S = X).  On a log axis the EX coordinate is ln(X / spot), as in the log
+// scheme: a small number, so the cell fraction keeps its bits (ln X itself would
+// lose about three of them to the offset).
+template <typename R, int AXIS, bool EX>
+__device__ __forceinline__ Look<R> lookup_state(R v, const R *trow, R inv_du, R a_off, R inv_spot, R amax,
+                                                R spot) {
+    if (!EX) return lookup<R, AXIS>(v, trow, inv_du, a_off, amax, spot);
+    Look<R> L = lookup_at<R>(AXIS == 0 ? v : Math<R>::lg(v * inv_spot), trow, inv_du, a_off, amax);
+    L.S = v;
+    return L;
+}
+
 // Forward payoff taps at step n+1 (the state is y_{n+1}): wave sums of payoff
 // and payoff^2 in FP64 into the wave's LDS slot.
-template <typename R>
+template <typename R, bool EX>
 __device__ __forceinline__ void fwd_payoffs(const Args &a, int tap, R y, bool active, double *wpart,
                                             int wave, int lane) {
-    const double S = (double)((R)a.spot * Math<R>::ex(y));
+    const double S = EX ? (double)y : (double)((R)a.spot * Math<R>::ex(y));
     const int k0 = ldu(a.tap_first + tap), kc = ldu(a.tap_count + tap);
     for (int q = 0; q < kc; ++q) {
         const int k = k0 + q;
@@ -339,11 +361,13 @@ __device__ __forceinline__ void fwd_payoffs(const Args &a, int tap, R y, bool ac
     }
 }
 
-// Adjoint seeds at step n+1: lambda += scale sum_k w_k d payoff_k / d y (the
-// adjoint kernels carry lambda scaled by the fixed-point scale 2^F).
-template <typename R>
+// Adjoint seeds at step n+1: lambda += scale sum_k w_k d payoff_k / d state (the
+// adjoint kernels carry lambda scaled by the fixed-point scale 2^F); the state is y
+// (d payoff / d y = +-S in the money) or, with EX, X (d payoff / d X = +-1).
+template <typename R, bool EX>
 __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam, double scale) {
-    const R S = (R)a.spot * Math<R>::ex(y);
+    const R S = EX ? y : (R)a.spot * Math<R>::ex(y);
+    const R D = EX ? (R)1 : S;
     const double Sd = (double)S;
     const int k0 = ldu(a.tap_first + tap), kc = ldu(a.tap_count + tap);
     for (int q = 0; q < kc; ++q) {
@@ -351,9 +375,9 @@ __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam, doubl
         const double K = ldu(a.opt_strike + k);
         const R w = (R)(ldu(a.cot + ldu(a.opt_orig + k)) * scale);
         if (ldu(a.opt_put + k)) {
-            if (Sd < K) lam -= w * S;
+            if (Sd < K) lam -= w * D;
         } else {
-            if (Sd > K) lam += w * S;
+            if (Sd > K) lam += w * D;
         }
     }
     return lam;
@@ -444,7 +468,8 @@ __device__ __forceinline__ int fixed_point_bits(const Args &a, double qmax, int 
 // Forward kernel: price-only, or storing every state (split / stored adjoint).
 // --------------------------------------------------------------------------
 // FP32: at most 64 VGPRs, so that 8 waves fit per SIMD (the kernel is issue-bound)
-template <typename R, int AXIS, bool STORE>
+// EX: the Euler step on X itself (the state and the stored planes are X).
+template <typename R, int AXIS, bool STORE, bool EX>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
 k_fwd(Args a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -457,6 +482,7 @@ k_fwd(Args a) {
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
 
     const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
+    const R inv_spot = (R)(1.0 / a.spot);
     const R spot = (R)a.spot, amax = (R)(I - 1);
     TabStage<R> stg;
     int wcur = -1;
@@ -470,7 +496,7 @@ k_fwd(Args a) {
         const long long p = (long long)tile * blockDim.x + tid;
         const bool active = p < a.P;
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
-        R y = 0;
+        R y = EX ? spot : (R)0;
         int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int wi = 0; wi < nW; ++wi) {
             const int ws = wi * W, we = min(N, ws + W);
@@ -497,11 +523,12 @@ k_fwd(Args a) {
                     const int n = n0 + r;
                     if (n < N) {
                         const R *trow = tuse + 2 * (n - ws) * I;
-                        const Look<R> L = lookup<R, AXIS>(y, trow, inv_du, a_off, amax, spot);
-                        y = fma(L.s, fma(-hdt, L.s, z[r]), y);
+                        const Look<R> L = lookup_state<R, AXIS, EX>(y, trow, inv_du, a_off, inv_spot, amax, spot);
+                        if (EX) y = fma(L.s * y, z[r], y);
+                        else y = fma(L.s, fma(-hdt, L.s, z[r]), y);
                         if (STORE && active) ((R *)a.states)[(size_t)n * a.P + p] = y;
                         if (n + 1 == next_tap) {
-                            fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
+                            fwd_payoffs<R, EX>(a, tap, y, active, wpart, wave, lane);
                             ++tap;
                             next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
                         }
@@ -538,12 +565,12 @@ constexpr int RB = 8;
 // is in the money at its maturity (the seed test of the sweep, on the stored state).
 // A path for which this fails has lambda = 0 at every step and contributes exactly
 // nothing to the gradient or to delta.
-template <typename R>
+template <typename R, bool EX>
 __device__ bool path_live(const Args &a, const R *Y, size_t P, size_t p) {
     for (int t = 0; t < a.n_taps; ++t) {
         const int n = a.tap_step[t];
         const R y = Y[(size_t)(n - 1) * P + p];
-        const double Sd = (double)((R)a.spot * Math<R>::ex(y));
+        const double Sd = EX ? (double)y : (double)((R)a.spot * Math<R>::ex(y));
         const int k0 = ldu(a.tap_first + t), kc = ldu(a.tap_count + t);
         for (int q = 0; q < kc; ++q) {
             const int k = k0 + q;
@@ -555,7 +582,9 @@ __device__ bool path_live(const Args &a, const R *Y, size_t P, size_t p) {
     return false;
 }
 
-template <typename R, int AXIS, bool MAGIC>
+// EX: the Euler step on X (stored planes hold X): c_n = (X_{n+1} - X_n) / sigma_n and
+// d X_{n+1} / d X_n = 1 + c_n (sigma_n / X_n + d sigma / d X).
+template <typename R, int AXIS, bool MAGIC, bool EX>
 __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -578,7 +607,9 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
     constexpr bool magic = MAGIC;   // the launcher chose it: qmax <= Math<R>::MAGIC_MAX
     const double scd = ldexp(1.0, F), inv_sc = ldexp(1.0, -F);
     const R hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
+    const R inv_spot = (R)(1.0 / a.spot);
     const R spot = (R)a.spot, amax = (R)(I - 1);
+    const R y0 = EX ? spot : (R)0;   // the state at step 0
     const int K = a.K, KI1 = K * (I + 1), B = gridDim.x, T = blockDim.x;
     Acc *Hl = H + (tid % K) * (I + 1);   // this lane's copy of a histogram row
     const R *Y = (const R *)a.states;
@@ -601,7 +632,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
             const int t = c0 + k * B;
             if (t >= a.n_tiles) break;
             const long long p = (long long)t * T + tid;
-            const bool live = p < a.P && (a.dense || path_live<R>(a, Y, P, (size_t)p));
+            const bool live = p < a.P && (a.dense || path_live<R, EX>(a, Y, P, (size_t)p));
             const unsigned long long m = __ballot(live);
             if (lane == 0) wcnt[wave] = __popcll(m);
             __syncthreads();
@@ -680,14 +711,22 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         if (FULL || n0 + r < N) {
-                            const R yr = (n0 + r == 0) ? (R)0 : y[r];
+                            const R yr = (n0 + r == 0) ? y0 : y[r];
                             yup[r] = (r == 3 || (!FULL && n0 + r + 1 >= N)) ? y_next : y[r + 1];
-                            L[r] = lookup<R, AXIS>(yr, tuse + 2 * (wn0 + r) * I, inv_du, a_off, amax,
-                                                   spot);
-                            cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
-                            R d = L[r].in ? L[r].d * inv_du : (R)0;
-                            if (AXIS == 0) d *= L[r].S;
-                            dsd[r] = d;
+                            L[r] = lookup_state<R, AXIS, EX>(yr, tuse + 2 * (wn0 + r) * I, inv_du, a_off,
+                                                             inv_spot, amax, spot);
+                            if (EX) {
+                                cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s);
+                                // sigma / X + d sigma / d X; on a log axis d sigma / d X = (d / du) / X
+                                R d = L[r].in ? L[r].d * inv_du : (R)0;
+                                if (AXIS == 0) d *= yr;
+                                dsd[r] = (L[r].s + d) * Math<R>::rcp(yr);
+                            } else {
+                                cc[r] = (yup[r] - yr) * Math<R>::rcp(L[r].s) - hdt * L[r].s;
+                                R d = L[r].in ? L[r].d * inv_du : (R)0;
+                                if (AXIS == 0) d *= L[r].S;
+                                dsd[r] = d;
+                            }
                         }
                     }
 #pragma unroll
@@ -695,7 +734,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
                         const int n = n0 + r;
                         if (FULL || n < N) {
                             if (n + 1 == cur_tap) {
-                                lam = rev_seeds<R>(a, tap, yup[r], lam, scd);
+                                lam = rev_seeds<R, EX>(a, tap, yup[r], lam, scd);
                                 if (!active) lam = 0;
                                 --tap;
                                 cur_tap = tap >= 0 ? a.tap_step[tap] : -1;
@@ -706,7 +745,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
                         }
                         hrow -= KI1;
                     }
-                    if (FULL || n0 < N) y_next = (n0 == 0) ? (R)0 : y[0];
+                    if (FULL || n0 < N) y_next = (n0 == 0) ? y0 : y[0];
                 };
                 auto block = [&](int b, auto full_tag) {
                     load_block(max(b - 1, 0), nxt);
@@ -726,7 +765,8 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
             }
             __syncthreads();
             fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
-            const double l0 = wave_sum(active ? (double)lam * inv_sc : 0.0);
+            // the adjoint of y_0 = ln(X_0 / spot): with EX, lambda is that of X_0 = spot
+            const double l0 = wave_sum(active ? (double)lam * inv_sc * (EX ? a.spot : 1.0) : 0.0);
             if (lane == 0) wlam[wave] += l0;
         }
     }
@@ -816,7 +856,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                                                               a_off, amax, spot);
                             y = fma(L.s, fma(-hdt, L.s, z[r]), y);
                             if (n + 1 == next_tap) {
-                                fwd_payoffs<R>(a, tap, y, active, wpart, wave, lane);
+                                fwd_payoffs<R, false>(a, tap, y, active, wpart, wave, lane);
                                 ++tap;
                                 next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
                             }
@@ -888,7 +928,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     const int n = na + k;
                     if (n < N) {
                         if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R>(a, rtap, y_next, lam, scd);
+                            lam = rev_seeds<R, false>(a, rtap, y_next, lam, scd);
                             if (!active) lam = 0;
                             --rtap;
                             cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
@@ -1065,28 +1105,29 @@ static void allow_lds(Kern kernel, size_t lds) {
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(block), lds, st, a);                         \
     } while (0)
 
+template <typename R, int AXIS, bool EX>
+static void fwd_as(const Args &a, bool store, int blocks, int block, size_t lds, hipStream_t st, Ev ev) {
+    if (store) LAUNCH((k_fwd<R, AXIS, true, EX>), blocks, block, lds, st, a);
+    else LAUNCH((k_fwd<R, AXIS, false, EX>), blocks, block, lds, st, a);
+}
+
+template <typename R>
+static void fwd_of(const Args &a, bool store, int blocks, int block, hipStream_t st, Ev ev) {
+    const size_t lds = lds_of<R>(store ? FWD_STORE : FWD_PRICE, a, block, a.W);
+    const bool ex = a.scheme == 1;
+    if (a.axis == 0) {
+        if (ex) fwd_as<R, 0, true>(a, store, blocks, block, lds, st, ev);
+        else fwd_as<R, 0, false>(a, store, blocks, block, lds, st, ev);
+    } else {
+        if (ex) fwd_as<R, 1, true>(a, store, blocks, block, lds, st, ev);
+        else fwd_as<R, 1, false>(a, store, blocks, block, lds, st, ev);
+    }
+}
+
 hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int block, hipStream_t st,
                       Ev ev) {
-    const int v = store ? FWD_STORE : FWD_PRICE;
-    if (precision == 64) {
-        const size_t lds = lds_of<double>(v, a, block, a.W);
-        if (a.axis == 0) {
-            if (store) LAUNCH((k_fwd<double, 0, true>), blocks, block, lds, st, a);
-            else LAUNCH((k_fwd<double, 0, false>), blocks, block, lds, st, a);
-        } else {
-            if (store) LAUNCH((k_fwd<double, 1, true>), blocks, block, lds, st, a);
-            else LAUNCH((k_fwd<double, 1, false>), blocks, block, lds, st, a);
-        }
-    } else {
-        const size_t lds = lds_of<float>(v, a, block, a.W);
-        if (a.axis == 0) {
-            if (store) LAUNCH((k_fwd<float, 0, true>), blocks, block, lds, st, a);
-            else LAUNCH((k_fwd<float, 0, false>), blocks, block, lds, st, a);
-        } else {
-            if (store) LAUNCH((k_fwd<float, 1, true>), blocks, block, lds, st, a);
-            else LAUNCH((k_fwd<float, 1, false>), blocks, block, lds, st, a);
-        }
-    }
+    if (precision == 64) fwd_of<double>(a, store, blocks, block, st, ev);
+    else fwd_of<float>(a, store, blocks, block, st, ev);
     return hipGetLastError();
 }
 
@@ -1097,20 +1138,27 @@ static bool use_magic(const Args &a, int precision, int block) {
     return precision == 64 || qmax <= Math<float>::MAGIC_MAX;
 }
 
+template <typename R, bool MAGIC, bool EX>
+static void rev_as(const Args &a, int blocks, int block, size_t lds, hipStream_t st, Ev ev) {
+    if (a.axis == 0) LAUNCH((k_rev<R, 0, MAGIC, EX>), blocks, block, lds, st, a);
+    else LAUNCH((k_rev<R, 1, MAGIC, EX>), blocks, block, lds, st, a);
+}
+
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st, Ev ev) {
+    const bool ex = a.scheme == 1;
     if (precision == 64) {
         const size_t lds = lds_of<double>(REV_STORED, a, block, a.W);
-        if (a.axis == 0) LAUNCH((k_rev<double, 0, true>), blocks, block, lds, st, a);
-        else LAUNCH((k_rev<double, 1, true>), blocks, block, lds, st, a);
+        if (ex) rev_as<double, true, true>(a, blocks, block, lds, st, ev);
+        else rev_as<double, true, false>(a, blocks, block, lds, st, ev);
     } else {
         const size_t lds = lds_of<float>(REV_STORED, a, block, a.W);
         const bool m = use_magic(a, precision, block);
-        if (a.axis == 0) {
-            if (m) LAUNCH((k_rev<float, 0, true>), blocks, block, lds, st, a);
-            else LAUNCH((k_rev<float, 0, false>), blocks, block, lds, st, a);
+        if (m) {
+            if (ex) rev_as<float, true, true>(a, blocks, block, lds, st, ev);
+            else rev_as<float, true, false>(a, blocks, block, lds, st, ev);
         } else {
-            if (m) LAUNCH((k_rev<float, 1, true>), blocks, block, lds, st, a);
-            else LAUNCH((k_rev<float, 1, false>), blocks, block, lds, st, a);
+            if (ex) rev_as<float, false, true>(a, blocks, block, lds, st, ev);
+            else rev_as<float, false, false>(a, blocks, block, lds, st, ev);
         }
     }
     return hipGetLastError();

@@ -20,6 +20,20 @@ def npdf(x):
     return np.exp(-0.5 * np.asarray(x) ** 2) / SQRT2PI
 
 
+def euler_x_call_1step(S, K, a):
+    """Call on X_1 = S (1 + a Z), Z standard normal (one Euler step on X with
+    a = sigma sqrt(T)): X_1 is Gaussian with mean S and sd S a, so the price is
+    (S - K) Phi(d) + S a phi(d), d = (S - K) / (S a); its derivative in a is S phi(d)."""
+    d = (S - K) / (S * a)
+    return (S - K) * ndtr(d) + S * a * float(npdf(d)), S * float(npdf(d))
+
+
+def euler_x_second_moment(S, sigma, dt, n_steps):
+    """E[(X_N - S)^2] for X_{n+1} = X_n (1 + sigma sqrt(dt) Z_n), flat sigma: the
+    factors are independent with mean 1 and second moment 1 + sigma^2 dt."""
+    return S * S * ((1.0 + sigma * sigma * dt) ** n_steps - 1.0)
+
+
 def bs_call(S, K, V):
     """Undiscounted Black-Scholes call with total variance V = sigma^2 T."""
     S, K, V = np.asarray(S, float), np.asarray(K, float), np.asarray(V, float)

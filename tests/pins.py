@@ -35,13 +35,13 @@ from tests import closed_forms as cf
 SQRT_TAIL = math.sqrt(-2.0 * math.log(2.0 ** -24))   # largest |Z| the 23-bit uniform allows
 
 
-def _batch_stats(o, surface, book, n_steps, n_paths, n_batches, seed=0, spot=100.0):
+def _batch_stats(o, surface, book, n_steps, n_paths, n_batches, seed=0, spot=100.0, scheme=0):
     """Price and gradient by batch means: mean over batches and the standard error
     of that mean, for the weighted book value."""
     per = n_paths // n_batches
     vals, grads = [], []
     for b in range(n_batches):
-        s = o.sums(surface, book, n_steps, seed, [(b * per, (b + 1) * per)], spot=spot)
+        s = o.sums(surface, book, n_steps, seed, [(b * per, (b + 1) * per)], spot=spot, scheme=scheme)
         vals.append(float(np.dot(book.weight, s["sum_pay"])) / per)
         grads.append(s["sum_grad"] / per)
     vals, grads = np.array(vals), np.array(grads)
@@ -354,26 +354,66 @@ def pin_two_steps(o, n_paths=1 << 17, n_batches=32):
 # --------------------------------------------------------------------------
 # adjoint against bump-and-reprice
 # --------------------------------------------------------------------------
-def crn_fd_grad(o, surface, book, n_paths, n_steps, seed, eps=1e-5):
+def crn_fd_grad(o, surface, book, n_paths, n_steps, seed, eps=1e-5, scheme=0):
     """Central bump of every node, (value(p+eps/2) - value(p-eps/2)) / eps, on the same
     random streams, of the weighted book value (the oracle's bumping estimator)."""
-    return o.bump_grad(surface, book, n_paths, n_steps, seed, eps).reshape(surface.sigma.shape)
+    return o.bump_grad(surface, book, n_paths, n_steps, seed, eps, scheme=scheme).reshape(surface.sigma.shape)
+
+
+# --------------------------------------------------------------------------
+# the Euler step on X itself (scheme 1)
+# --------------------------------------------------------------------------
+def pin_euler_x_one_step(o, n_paths=1 << 17):
+    """One Euler step on X: X_1 = S0 (1 + s_0 sqrt(T) Z) is Gaussian, so the call price
+    is closed form and d price / d node = S0 phi(d) sqrt(T) w_node(S0, 0); nodes off the
+    cell are zero."""
+    for kind in (W.LIN, W.LOG):
+        s = W.tiny_surface(kind, 6, 3, seed=9)
+        T, K = 0.25, 103.0
+        r = o.price_and_grad(s, W.call(K, T), n_paths, 1, seed=2, scheme=1)
+        s0, _, (i, j), w = o.interp(s, 100.0, 0.0)
+        exact, d_da = cf.euler_x_call_1step(100.0, K, s0 * math.sqrt(T))
+        assert abs(r["price"][0] - exact) < 4 * r["stderr"][0], (kind, r["price"][0], exact)
+        _, _, g, g_se = _batch_stats(o, s, W.call(K, T), 1, n_paths, 32, seed=2, scheme=1)
+        expect = np.zeros_like(s.sigma)
+        for (di, dj), wk in zip([(0, 0), (1, 0), (0, 1), (1, 1)], w):
+            expect[i + di, j + dj] += d_da * math.sqrt(T) * wk
+        mask = expect != 0
+        assert np.all(np.abs(g[mask] - expect[mask]) < 4 * g_se[mask] + 1e-12), (kind, g, expect)
+        assert np.all(r["grad"][~mask] == 0.0)
+
+
+def pin_euler_x_moments(o, n_paths=1 << 17):
+    """Flat sigma, Euler on X: E[X_N] = S0 and E[(X_N - S0)^2] = S0^2 ((1 + sigma^2 dt)^N
+    - 1), where the log scheme has S0^2 (exp(sigma^2 T) - 1) (10% apart here).  A call
+    and a put at K = S0 give X - K = call - put and (X - K)^2 = call^2 + put^2."""
+    sig, N, T = 0.6, 2, 1.0
+    s = W.flat_surface(W.small_surface(), sig)
+    book = W.Book([0, 1], [100.0, 100.0], [T, T], [1.0, 1.0])
+    r = o.sums(s, book, N, 3, [(0, n_paths)], want_grad=False, scheme=1)
+    m1 = (r["sum_pay"][0] - r["sum_pay"][1]) / n_paths
+    m2 = (r["sum_pay2"][0] + r["sum_pay2"][1]) / n_paths
+    exact = cf.euler_x_second_moment(100.0, sig, T / N, N)
+    assert abs(m1) < 4 * math.sqrt(m2 / n_paths), m1
+    assert abs(m2 - exact) < 0.03 * exact, (m2, exact)
+    lognormal = 100.0 ** 2 * (math.exp(sig * sig * T) - 1.0)
+    assert abs(lognormal - exact) > 0.08 * exact
 
 
 def pin_adjoint_fd(o):
     book = W.Book([0, 1, 0], [100.0, 105.0, 92.0], [1.0, 0.5, 0.75], [1.0, 2.5, -0.7])
-    for kind in (W.LIN, W.LOG):
+    for kind, scheme in ((W.LIN, 0), (W.LOG, 0), (W.LIN, 1), (W.LOG, 1)):
         s = W.tiny_surface(kind, 5, 4, seed=21 + kind)
-        r = o.price_and_grad(s, book, 512, 8, seed=6)
-        fd = crn_fd_grad(o, s, book, 512, 8, seed=6)
+        r = o.price_and_grad(s, book, 512, 8, seed=6, scheme=scheme)
+        fd = crn_fd_grad(o, s, book, 512, 8, seed=6, scheme=scheme)
         scale = np.abs(r["grad"]).max()
         assert scale > 0.1
         err = np.abs(r["grad"] - fd).max()
-        assert err < 2e-6 * scale, (kind, err, scale)
+        assert err < 2e-6 * scale, (kind, scheme, err, scale)
         # delta against a central bump of the spot
         h = 1e-4
-        up = o.price_and_grad(s, book, 512, 8, seed=6, spot=100.0 + h, want_grad=False)
-        dn = o.price_and_grad(s, book, 512, 8, seed=6, spot=100.0 - h, want_grad=False)
+        up = o.price_and_grad(s, book, 512, 8, seed=6, spot=100.0 + h, want_grad=False, scheme=scheme)
+        dn = o.price_and_grad(s, book, 512, 8, seed=6, spot=100.0 - h, want_grad=False, scheme=scheme)
         fd_delta = (np.dot(book.weight, up["price"]) - np.dot(book.weight, dn["price"])) / (2 * h)
         assert abs(r["delta"] - fd_delta) < 1e-6 * max(1.0, abs(fd_delta)), (r["delta"], fd_delta)
 
@@ -404,4 +444,4 @@ def pin_zero_buckets(o):
 
 FAST_PINS = [pin_uniform, pin_box_muller, pin_interp, pin_flat_black_scholes,
              pin_flat_pathwise_vega, pin_put_call_parity, pin_adjoint_fd, pin_term_structure,
-             pin_one_step]
+             pin_one_step, pin_euler_x_one_step, pin_euler_x_moments]

@@ -135,3 +135,12 @@ def test_planned_histogram_window_fits_lds():
                         assert st in (_lib.LV_OK, _lib.LV_ERR_UNSUPPORTED), (prec, block, k, win, st)
                         n_ok += st == _lib.LV_OK
     assert n_ok > 100
+
+
+def test_check_scheme_options():
+    """The Euler step on X is planned for the stored and price-only modes; an unknown
+    scheme is an argument error and checkpoints with it are refused."""
+    assert lv.check(**_req(), scheme="euler_x") == _lib.LV_OK
+    assert lv.check(**_req(), scheme="euler_x", adjoint="none") == _lib.LV_OK
+    assert lv.check(**_req(), scheme=7) == _lib.LV_ERR_ARG
+    assert lv.check(**_req(), scheme="euler_x", adjoint="checkpoint") == _lib.LV_ERR_UNSUPPORTED

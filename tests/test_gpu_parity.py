@@ -156,6 +156,55 @@ def test_book_log_axis_ragged(lv, ctx, orc, precision, adjoint):
     assert_parity(got, ref, precision, f"book {precision} {adjoint}")
 
 
+@pytest.mark.parametrize("precision,axis", [(32, "lin"), (64, "lin"), (32, "log"), (64, "log")])
+def test_euler_x_scheme(lv, ctx, orc, precision, axis):
+    """The explicit Euler step on X itself (scheme euler_x) against the oracle's scheme 1,
+    stored adjoint: the linear 21 x 13 grid with one call, and the log-spaced 60 x 30
+    grid with calls and puts of uneven maturity, a ragged path count and 156 steps;
+    the price-only run gives the same prices."""
+    if axis == "lin":
+        wl = W.small_call()
+        surf, book, P, N, seed = wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed
+    else:
+        surf, book, P, N, seed = W.book_surface(0), mixed_book(), 20000 + 37, 156, 3
+    s = surf.rounded_to_f32() if precision == 32 else surf
+    ref = orc.price_and_grad(s, book, P, N, seed=seed, scheme=1)
+    got = gpu_run(lv, ctx, surf, book, P, N, seed, precision=precision, scheme="euler_x")
+    assert_parity(got, ref, precision, f"euler_x {axis} {precision}")
+    p, _, _, _ = lv.price_and_grad(surf, 100.0, book.strike, book.maturity, P, N, seed, is_put=book.is_put,
+                                   weights=book.weight, ctx=ctx, precision=precision, scheme="euler_x",
+                                   adjoint="none", want_grad=False)
+    assert np.array_equal(p, got["price"])
+    # the two schemes are different estimators of the same model
+    lg = gpu_run(lv, ctx, surf, book, P, N, seed, precision=precision)
+    assert not np.array_equal(lg["price"], got["price"])
+
+
+@pytest.mark.parametrize("scheme", ["log_euler", "euler_x"])
+def test_grid_30x60(lv, ctx, orc, scheme):
+    """The paper's grid orientation, 30 spot by 60 time nodes (log-spaced spots, 3 years),
+    with a call and a put: FP32 stored adjoint against the oracle.  2^17 paths: FP32's
+    cell flips (a path on the other side of a node than in FP64 takes the other cell's
+    slope) move buckets by noise that shrinks as 1/sqrt(paths)."""
+    sa, ta = W.Axis(30, W.LOG, 40.0, 250.0), W.Axis(60, W.LIN, 0.0, 3.0)
+    surf = W.Surface(sa, ta, W.noisy(W.smile_surface(sa, ta, 0.12, 0.12, decay=False), 0.005, 4))
+    book = W.Book([0, 1], [100.0, 90.0], [3.0, 1.5], [1.0, 0.5])
+    P, N = (1 << 17) + 5, 156
+    ref = orc.price_and_grad(surf.rounded_to_f32(), book, P, N, seed=5, scheme=W_SCHEME[scheme])
+    got = gpu_run(lv, ctx, surf, book, P, N, 5, precision=32, scheme=scheme)
+    assert_parity(got, ref, 32, f"30x60 {scheme}")
+
+
+W_SCHEME = {"log_euler": 0, "euler_x": 1}
+
+
+def test_euler_x_refuses_checkpoints(lv, ctx):
+    wl = W.small_call()
+    with pytest.raises(lv.LVError, match="UNSUPPORTED"):
+        gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, precision=32, scheme="euler_x",
+                adjoint="checkpoint")
+
+
 @pytest.mark.parametrize("P,N", [(2, 1), (3, 2), (1000, 13), (257, 5)])
 def test_degenerate_shapes(lv, ctx, orc, P, N):
     surf = W.tiny_surface(W.LIN, 5, 4, seed=1)

@@ -33,11 +33,17 @@ MUTANTS = {
     "put_derivative_sign": ("if (pb->is_put[k]) return K > S ? -S : 0.0;", "if (pb->is_put[k]) return K > S ? S : 0.0;"),
     "payoff_at_last_step": ("payoffs[k] = lvo_payoff(pb, k, w->y[pb->tap_step[k]]);", "payoffs[k] = lvo_payoff(pb, k, w->y[N]);"),
     "cotangent_weight_ignored": ("double wk = pb->weight ? pb->weight[k] : 1.0;", "double wk = 1.0;"),
+    "euler_x_lognormal_step": ("X[n + 1] = X[n] + w->iv[n].sigma * X[n] * sdt * w->z[n];",
+                               "X[n + 1] = X[n] * exp(w->iv[n].sigma * sdt * w->z[n] - 0.5 * w->iv[n].sigma * w->iv[n].sigma * dt);"),
+    "euler_x_c_without_X": ("double c = X[n - 1] * sdt * w->z[n - 1];", "double c = sdt * w->z[n - 1];"),
+    "euler_x_no_spot_slope": ("(iv->sigma + iv->dsigma_dy)", "(iv->sigma)"),
+    "euler_x_wrong_node": ("grad[q00 + 1] += lam * c * iv->w[2];", "grad[q00 + J + 1] += lam * c * iv->w[2];"),
 }
 
 BATTERY = [pins.pin_uniform, pins.pin_box_muller, pins.pin_interp, pins.pin_flat_pathwise_vega,
            pins.pin_one_step, pins.pin_adjoint_fd, pins.pin_put_call_parity,
-           pins.pin_flat_black_scholes, pins.pin_term_structure]
+           pins.pin_flat_black_scholes, pins.pin_term_structure, pins.pin_euler_x_one_step,
+           pins.pin_euler_x_moments]
 
 
 def _build_mutant(name, old, new, tmpdir):
