@@ -260,6 +260,9 @@ def main():
         msc, oc = timed(max(3, args.steps // 2), adjoint="checkpoint")
         variants["fp32_checkpoint"] = {"ms_per_step": msc, "value": P * N / (msc * 1e-3),
                                        "max_bucket_err_vs_stored": float(np.abs(oc[2].cpu().numpy() - grad32).max() / np.abs(grad32).max())}
+        mse, oe = timed(args.steps, scheme="euler_x")
+        variants["fp32_euler_step_on_price"] = {"ms_per_step": mse, "value": P * N / (mse * 1e-3),
+                                                "price": float(oe[0].cpu().numpy().ravel()[0])}
         msd, od = timed(max(3, args.steps // 2), dense_adjoint=True)
         variants["fp32_every_path_reverse"] = {
             "ms_per_step": msd, "value": P * N / (msd * 1e-3),
