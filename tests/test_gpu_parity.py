@@ -426,6 +426,20 @@ def test_bump_and_reprice(lv, ctx, orc):
     assert err32 < 5e-3
 
 
+def test_bump_and_reprice_rejects_bad_arguments(lv, ctx):
+    """A bump that is not finite and positive, or a negative batch, is an argument error
+    raised before any launch."""
+    import torch
+    s = W.small_surface()
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device="cuda")
+    kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, ctx=ctx)
+    for eps in (0.0, -1e-3, float("nan"), float("inf")):
+        with pytest.raises(lv.LVError, match="ARG"):
+            lv.bump_grad_dev(sig, 100.0, [100.0], [1.0], 1024, 52, 0, eps=eps, **kw)
+    with pytest.raises(lv.LVError, match="ARG"):
+        lv.bump_grad_dev(sig, 100.0, [100.0], [1.0], 1024, 52, 0, eps=1e-3, batch=-1, **kw)
+
+
 def test_full_size_single_call_60x30(lv, ctx, orc):
     """The benchmark workload at full size (2^19 paths, 156 steps, 60 x 30 grid) in the
     benchmark's launch configuration.  FP64 kernels: the tight bar.  FP32 kernels:
