@@ -304,10 +304,11 @@ __device__ __forceinline__ Look<R> lookup_at(R x, const R *trow, R inv_du, R a_o
     Look<R> L;
     L.S = 0;
     const R a = fma(x, inv_du, a_off);
-    L.in = (a > (R)0) && (a < amax);
     const R ac = clamp_to(a, amax);
     // i = I - 1 only at (or beyond) the top node: there f = 0 and the table's d = 0,
-    // so the value is the node's and the term for node i + 1 is zero
+    // so the value is the node's, the term for node i + 1 is zero and so is the slope;
+    // below the range ac = 0.  So "strictly inside" is ac > 0 (the top needs no test).
+    L.in = ac > (R)0;
     L.i = (int)ac;
     L.f = ac - (R)L.i;
     const R c = trow[2 * L.i], d = trow[2 * L.i + 1];
