@@ -263,6 +263,19 @@ def main():
         mse, oe = timed(args.steps, scheme="euler_x")
         variants["fp32_euler_step_on_price"] = {"ms_per_step": mse, "value": P * N / (mse * 1e-3),
                                                 "price": float(oe[0].cpu().numpy().ravel()[0])}
+        # the TPU runs' mixed precision held sigma in bfloat16 for the interpolation
+        # (Sec. IV-D); the same rounding of the nodes here, with its effect on the
+        # estimates next to FP32's own distance from FP64 on the same paths
+        msh, oh = timed(args.steps, sigma_bf16=True)
+        ph, gh = oh[0].cpu().numpy(), oh[2].cpu().numpy()
+        gscale = np.abs(g64).max()
+        variants["fp32_sigma_nodes_bf16"] = {
+            "ms_per_step": msh, "value": P * N / (msh * 1e-3),
+            "price_diff_vs_fp64": float(np.abs(ph - p64).max()),
+            "max_bucket_diff_vs_fp64": float(np.abs(gh - g64).max() / gscale),
+            "fp32_price_diff_vs_fp64": float(np.abs(price32 - p64).max()),
+            "fp32_max_bucket_diff_vs_fp64": float(np.abs(grad32 - g64).max() / gscale),
+            "price_std_err": float(se32.max())}
         msd, od = timed(max(3, args.steps // 2), dense_adjoint=True)
         variants["fp32_every_path_reverse"] = {
             "ms_per_step": msd, "value": P * N / (msd * 1e-3),

@@ -130,6 +130,13 @@ typedef struct {
                                Sec. IV-A narrates the scheme (stored and price-only adjoint modes;
                                LV_ERR_UNSUPPORTED with LV_ADJ_CHECKPOINT).  The split calls
                                lv_forward_dev / lv_backward_dev step log-Euler. */
+    int32_t sigma_bf16;     /* 1: round every node of sigma to bfloat16 (FP64 -> FP32 -> bfloat16,
+                               each to nearest with ties to even) before the vol table is built:
+                               the precision in which the paper's mixed-precision TPU runs hold
+                               sigma for the matrix-unit interpolation (Sec. IV-D).  Prices and
+                               gradients are then those of the rounded surface, the gradient
+                               being taken with respect to its nodes.  0 (default): sigma as
+                               given; any other value is LV_ERR_ARG */
 } lv_opts;
 
 enum { LV_SCHEME_LOG_EULER = 0, LV_SCHEME_EULER_X = 1 };

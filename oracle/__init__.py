@@ -91,6 +91,8 @@ class Oracle:
         L.lvo_interp_at.argtypes = surf + [C.c_double, C.c_double, C.POINTER(C.c_double),
                                            C.POINTER(C.c_double), _ip, _dp]
         L.lvo_interp_at.restype = C.c_int
+        L.lvo_round_bf16.argtypes = [C.c_double]
+        L.lvo_round_bf16.restype = C.c_double
 
     def _check(self, rc):
         if rc != 0:
@@ -112,6 +114,13 @@ class Oracle:
         out = np.zeros((n_paths, n_steps))
         self.lib.lvo_normals(seed, p0, n_paths, n_steps, out)
         return out
+
+    # -- reduced precision of the nodes ------------------------------------
+    def round_bf16(self, sigma) -> np.ndarray:
+        """Every node rounded to bfloat16 by way of single precision (Sec. IV-D's
+        mixed-precision TPU runs hold sigma in bfloat16 for the interpolation)."""
+        sigma = np.asarray(sigma, dtype=np.float64)
+        return np.array([self.lib.lvo_round_bf16(float(v)) for v in sigma.ravel()]).reshape(sigma.shape)
 
     # -- interpolation -----------------------------------------------------
     def interp(self, surface, S: float, t: float):

@@ -561,3 +561,38 @@ int lvo_interp_at(int32_t n_spot, int32_t spot_kind, double spot_lo, double spot
     memcpy(w4, iv.w, sizeof(double) * 4);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Reduced precision of the vol nodes (Sec. IV-D: the TPU runs keep sigma in  */
+/* bfloat16 for the matrix-unit interpolation).  bfloat16 keeps the sign, the */
+/* 8 exponent bits and the top 7 fraction bits of an IEEE single, so its      */
+/* values are the singles whose low 16 bits are zero.  A node goes to single  */
+/* precision first (to nearest, as a C cast does) and then to the nearer of   */
+/* the two bfloat16 values that bracket it; at an exact tie, to the one whose */
+/* last kept fraction bit is zero.  Finite inputs only.                       */
+/* ------------------------------------------------------------------------- */
+static float lvo_bits_to_float(uint32_t u)
+{
+    float f;
+    memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+double lvo_round_bf16(double v)
+{
+    const float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    const uint32_t sign = u & 0x80000000u, mag = u & 0x7FFFFFFFu;
+    const uint32_t below = mag & 0xFFFF0000u;    /* bracketing bfloat16 magnitudes */
+    const uint32_t above = below + 0x10000u;     /* (the next one up carries into the exponent) */
+    if (below == mag) return (double)f;          /* already a bfloat16 value */
+    const double x = (double)lvo_bits_to_float(mag);
+    const double lo = (double)lvo_bits_to_float(below), hi = (double)lvo_bits_to_float(above);
+    const double d_lo = x - lo, d_hi = hi - x;   /* exact: all three are singles */
+    uint32_t pick;
+    if (d_lo < d_hi) pick = below;
+    else if (d_hi < d_lo) pick = above;
+    else pick = (below & 0x10000u) ? above : below;
+    return (double)lvo_bits_to_float(sign | pick);
+}

@@ -80,14 +80,17 @@ SCHEME = {"log_euler": 0, "euler_x": 1}
 
 def make_opts(precision=32, adjoint="stored", ckpt_every=16, use_graph=False, block=0,
               blocks_per_cu=0, copies=0, window=0, profile=False, autotune=False, fwd_block=0,
-              fwd_blocks_per_cu=0, dense_adjoint=False, profile_kinds=0, scheme="log_euler") -> lv_opts:
-    """scheme: "log_euler" (the Euler step on ln X) or "euler_x" (on X itself)."""
+              fwd_blocks_per_cu=0, dense_adjoint=False, profile_kinds=0, scheme="log_euler",
+              sigma_bf16=False) -> lv_opts:
+    """scheme: "log_euler" (the Euler step on ln X) or "euler_x" (on X itself).
+    sigma_bf16: price the surface with its nodes rounded to bfloat16 (the TPU's storage
+    precision for the interpolation, Sec. IV-D)."""
     adj = ADJOINT[adjoint] if isinstance(adjoint, str) else int(adjoint)
     sch = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     return lv_opts(int(precision), adj, int(ckpt_every), int(bool(use_graph)), int(block),
                    int(blocks_per_cu), int(copies), int(window), int(bool(profile)),
                    int(bool(autotune)), int(fwd_block), int(fwd_blocks_per_cu),
-                   int(bool(dense_adjoint)), int(profile_kinds), sch)
+                   int(bool(dense_adjoint)), int(profile_kinds), sch, int(sigma_bf16))
 
 
 def option_order(maturities, n_steps) -> np.ndarray:

@@ -43,7 +43,8 @@ class lv_opts(C.Structure):
                 ("use_graph", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("copies", C.c_int32), ("window", C.c_int32), ("profile", C.c_int32),
                 ("autotune", C.c_int32), ("fwd_block", C.c_int32), ("fwd_blocks_per_cu", C.c_int32),
-                ("dense_adjoint", C.c_int32), ("profile_kinds", C.c_int32), ("scheme", C.c_int32)]
+                ("dense_adjoint", C.c_int32), ("profile_kinds", C.c_int32), ("scheme", C.c_int32),
+                ("sigma_bf16", C.c_int32)]
 
 
 class lv_run_info(C.Structure):

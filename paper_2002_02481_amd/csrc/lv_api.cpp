@@ -44,6 +44,7 @@ struct Plan {
     int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, bpc = 2, CH = 1;
     int dense = 0;   // reverse kernel sweeps every path (not only those with a nonzero adjoint)
     int scheme = 0;  // 0: Euler on ln X; 1: Euler on X
+    int bf16 = 0;    // 1: sigma rounded to bfloat16 before the table is built
     int fblock = 256, fblocks = 0, f_n_tiles = 0, fbpc = 2;
     int G = 0, Q = 0;
     Shape user{0, 0, 0, 0, 0, 0};   // caller-fixed shape fields (0 = free)
@@ -310,6 +311,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
         return fail(ctx, LV_ERR_ARG, "unknown scheme %d", o.scheme);
     if (o.scheme == LV_SCHEME_EULER_X && o.adjoint == LV_ADJ_CHECKPOINT)
         return fail(ctx, LV_ERR_UNSUPPORTED, "the Euler step on X runs with the stored or no adjoint");
+    if (o.sigma_bf16 != 0 && o.sigma_bf16 != 1) return fail(ctx, LV_ERR_ARG, "sigma_bf16 must be 0 or 1");
     if (o.ckpt_every == 0) o.ckpt_every = 16;
     if (o.ckpt_every != 8 && o.ckpt_every != 16 && o.ckpt_every != 32)
         return fail(ctx, LV_ERR_ARG, "ckpt_every must be 8, 16 or 32");
@@ -344,6 +346,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     pl.profile = o.profile ? (o.profile_kinds ? o.profile_kinds : (1 << LV_K_COUNT) - 1) : 0;
     pl.dense = o.dense_adjoint ? 1 : 0;
     pl.scheme = o.scheme;
+    pl.bf16 = o.sigma_bf16;
     pl.G = (int)G;
     pl.Q = 2 * pl.n_opt + 1 + pl.G;
 
@@ -524,6 +527,7 @@ lvk::Args make_args(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *
     a.CH = pl.CH;
     a.dense = pl.dense;
     a.scheme = pl.scheme;
+    a.sigma_bf16 = pl.bf16;
     a.seg = pl.seg;
     return a;
 }
@@ -660,7 +664,7 @@ std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf
     char buf[128];
     snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%llu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%d|", pl.I,
              pl.J, pl.N, pl.axis, pl.P, (unsigned long long)pl.seed, pl.precision, pl.adjoint, pl.seg, pl.block,
-             pl.blocks, pl.W, pl.WH, pl.K, pl.CH, pl.dense * 2 + pl.scheme, pl.fblock, pl.fblocks, pl.spot, pl.dt,
+             pl.blocks, pl.W, pl.WH, pl.K, pl.CH, (pl.dense * 2 + pl.scheme) * 2 + pl.bf16, pl.fblock, pl.fblocks, pl.spot, pl.dt,
              n_surf);
     k += buf;
     k += adjoint ? "A|" : "F|";

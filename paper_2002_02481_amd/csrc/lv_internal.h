@@ -48,6 +48,7 @@ struct Args {
     int dense;                  // reverse kernel: sweep every path, not only live ones
     int seg;                    // checkpoint segment (steps)
     int scheme;                 // 0: Euler on y = ln(X/X0); 1: Euler on X (stored states hold X)
+    int sigma_bf16;             // 1: the table is built from sigma rounded to bfloat16
 };
 
 enum Variant { FWD_PRICE = 0, FWD_STORE = 1, REV_STORED = 2, FUSED_CKPT = 3 };

@@ -215,15 +215,26 @@ __global__ void k_table(Args a) {
     const int I = a.I, J = a.J;
     const long long ne = (long long)a.N * I;
     R *t = (R *)const_cast<void *>(a.gtab);
+    const double *s = a.sigma;
+    // node value: as given, or rounded to bfloat16 by way of FP32 (both roundings to
+    // nearest, ties to even; bfloat16 is the upper half of an FP32 word, so adding
+    // 0x7fff plus the kept word's lowest bit carries exactly when the dropped half is
+    // above one half, or equal to it with that bit set)
+    auto node = [&](int k) -> double {
+        const double v = s[k];
+        if (!a.sigma_bf16) return v;
+        unsigned u = __float_as_uint((float)v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (double)__uint_as_float(u & 0xffff0000u);
+    };
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
          e += (long long)gridDim.x * blockDim.x) {
         const int n = (int)(e / I), i = (int)(e - (long long)n * I);
         const int j = a.tj[n];
         const double al = a.ta[n];
-        const double *s = a.sigma;
-        const double c0 = (1.0 - al) * s[i * J + j] + al * s[i * J + j + 1];
+        const double c0 = (1.0 - al) * node(i * J + j) + al * node(i * J + j + 1);
         double c1 = c0;
-        if (i + 1 < I) c1 = (1.0 - al) * s[(i + 1) * J + j] + al * s[(i + 1) * J + j + 1];
+        if (i + 1 < I) c1 = (1.0 - al) * node((i + 1) * J + j) + al * node((i + 1) * J + j + 1);
         t[2 * e] = (R)c0;
         t[2 * e + 1] = (R)(c1 - c0);
     }

@@ -18,6 +18,8 @@ What pins what:
   * one and two steps     -- exact prices of the discrete scheme by integration
   * adjoint               -- central finite differences with common random numbers
   * zero buckets          -- nodes no path can reach are exactly zero
+  * bfloat16 nodes        -- torch's float32 -> bfloat16 conversion (a library routine),
+                             exact ties between neighbours, the two-step rounding
 """
 from __future__ import annotations
 
@@ -445,3 +447,30 @@ def pin_zero_buckets(o):
 FAST_PINS = [pin_uniform, pin_box_muller, pin_interp, pin_flat_black_scholes,
              pin_flat_pathwise_vega, pin_put_call_parity, pin_adjoint_fd, pin_term_structure,
              pin_one_step, pin_euler_x_one_step, pin_euler_x_moments]
+
+
+def pin_round_bf16(o):
+    """Vol nodes rounded to bfloat16 by way of single precision.  Checked against
+    torch's float32 -> bfloat16 conversion (round to nearest, ties to even) over six
+    decades; at every midpoint between neighbouring bfloat16 values in [1/16, 4) the
+    even neighbour is taken, one single ulp either side goes to the nearer one, and
+    bfloat16 values are fixed points; a double just above a midpoint (by less than half
+    a single ulp) first becomes the midpoint and so also goes to the even neighbour."""
+    import torch
+    r = np.random.default_rng(11)
+    x = np.concatenate([r.uniform(0.05, 1.5, 4000), np.exp(r.uniform(-7.0, 7.0, 4000))])
+    lib = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(o.round_bf16(x), lib)
+    bits = np.arange(0x3D80, 0x4080, dtype=np.uint32)            # bfloat16 patterns in [1/16, 4)
+    b = (bits << 16).view(np.float32).astype(np.float64)
+    lo, hi = b[:-1], b[1:]
+    mid = 0.5 * (lo + hi)                                         # exact in single precision
+    even = np.where((bits[:-1] & 1) == 0, lo, hi)
+    assert np.array_equal(o.round_bf16(mid), even)
+    mid32 = mid.astype(np.float32)
+    down = np.nextafter(mid32, np.float32(0)).astype(np.float64)
+    up = np.nextafter(mid32, np.float32(np.inf)).astype(np.float64)
+    assert np.array_equal(o.round_bf16(down), lo) and np.array_equal(o.round_bf16(up), hi)
+    assert np.array_equal(o.round_bf16(b), b)
+    ulp32 = np.spacing(mid32).astype(np.float64)
+    assert np.array_equal(o.round_bf16(mid + 0.25 * ulp32), even)

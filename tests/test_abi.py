@@ -144,3 +144,14 @@ def test_check_scheme_options():
     assert lv.check(**_req(), scheme="euler_x", adjoint="none") == _lib.LV_OK
     assert lv.check(**_req(), scheme=7) == _lib.LV_ERR_ARG
     assert lv.check(**_req(), scheme="euler_x", adjoint="checkpoint") == _lib.LV_ERR_UNSUPPORTED
+
+
+def test_check_sigma_bf16_option():
+    """Rounding the vol nodes to bfloat16 is a switch: 0 and 1 plan in every adjoint mode
+    and precision, anything else is an argument error."""
+    for adj in ("stored", "checkpoint", "none"):
+        for prec in (32, 64):
+            assert lv.check(**_req(), sigma_bf16=1, adjoint=adj, precision=prec) == _lib.LV_OK
+    assert lv.check(**_req(), sigma_bf16=0) == _lib.LV_OK
+    assert lv.check(**_req(), sigma_bf16=2) == _lib.LV_ERR_ARG
+    assert lv.check(**_req(), sigma_bf16=-1) == _lib.LV_ERR_ARG

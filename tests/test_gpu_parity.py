@@ -198,6 +198,31 @@ def test_grid_30x60(lv, ctx, orc, scheme):
 W_SCHEME = {"log_euler": 0, "euler_x": 1}
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+def test_sigma_bf16(lv, ctx, orc, precision):
+    """Vol nodes rounded to bfloat16 on the device (option sigma_bf16) on the log-spaced
+    60 x 30 grid with calls and puts of uneven maturity, a ragged path count and 156 steps:
+    against the oracle on its own rounding of the surface, and bit-identical to a run
+    handed that rounded surface with the option off, so the device's rounding is the
+    oracle's node for node.  Graph replays with the option on and off keep them apart."""
+    surf, book, P, N, seed = W.book_surface(0), mixed_book(), 20000 + 37, 156, 3
+    rounded = W.Surface(surf.spot_axis, surf.time_axis, orc.round_bf16(surf.sigma))
+    assert not np.array_equal(rounded.sigma, surf.sigma)
+    ref = orc.price_and_grad(rounded, book, P, N, seed=seed)
+    got = gpu_run(lv, ctx, surf, book, P, N, seed, precision=precision, sigma_bf16=True)
+    assert_parity(got, ref, precision, f"sigma_bf16 {precision}")
+    pre = gpu_run(lv, ctx, rounded, book, P, N, seed, precision=precision)
+    for k in ("price", "stderr", "grad"):
+        assert np.array_equal(got[k], pre[k]), k
+    assert got["delta"] == pre["delta"]
+    plain = gpu_run(lv, ctx, surf, book, P, N, seed, precision=precision)
+    assert not np.array_equal(plain["price"], got["price"])
+    if precision == 32:
+        for on, want in ((True, got), (False, plain), (True, got)):
+            g = gpu_run(lv, ctx, surf, book, P, N, seed, precision=32, sigma_bf16=on, use_graph=True)
+            assert np.array_equal(g["price"], want["price"]) and np.array_equal(g["grad"], want["grad"])
+
+
 def test_euler_x_refuses_checkpoints(lv, ctx):
     wl = W.small_call()
     with pytest.raises(lv.LVError, match="UNSUPPORTED"):

@@ -38,9 +38,13 @@ MUTANTS = {
     "euler_x_c_without_X": ("double c = X[n - 1] * sdt * w->z[n - 1];", "double c = sdt * w->z[n - 1];"),
     "euler_x_no_spot_slope": ("(iv->sigma + iv->dsigma_dy)", "(iv->sigma)"),
     "euler_x_wrong_node": ("grad[q00 + 1] += lam * c * iv->w[2];", "grad[q00 + J + 1] += lam * c * iv->w[2];"),
+    "bf16_truncates": ("if (d_lo < d_hi) pick = below;", "if (1) pick = below;"),
+    "bf16_ties_away": ("else pick = (below & 0x10000u) ? above : below;", "else pick = above;"),
+    "bf16_ties_odd": ("else pick = (below & 0x10000u) ? above : below;", "else pick = (below & 0x10000u) ? below : above;"),
+    "bf16_straight_from_double": ("const double x = (double)lvo_bits_to_float(mag);", "const double x = fabs(v);"),
 }
 
-BATTERY = [pins.pin_uniform, pins.pin_box_muller, pins.pin_interp, pins.pin_flat_pathwise_vega,
+BATTERY = [pins.pin_round_bf16, pins.pin_uniform, pins.pin_box_muller, pins.pin_interp, pins.pin_flat_pathwise_vega,
            pins.pin_one_step, pins.pin_adjoint_fd, pins.pin_put_call_parity,
            pins.pin_flat_black_scholes, pins.pin_term_structure, pins.pin_euler_x_one_step,
            pins.pin_euler_x_moments]

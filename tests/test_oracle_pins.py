@@ -20,6 +20,7 @@ def test_philox_matches_rocrand(orc):
     pins.pin_flat_pathwise_vega, pins.pin_flat_vega_and_columns, pins.pin_term_structure,
     pins.pin_put_call_parity, pins.pin_threads, pins.pin_one_step, pins.pin_two_steps,
     pins.pin_adjoint_fd, pins.pin_zero_buckets, pins.pin_euler_x_one_step, pins.pin_euler_x_moments,
+    pins.pin_round_bf16,
 ], ids=lambda f: f.__name__)
 def test_pin(orc, pin):
     pin(orc)
