@@ -263,6 +263,11 @@ def main():
         mse, oe = timed(args.steps, scheme="euler_x")
         variants["fp32_euler_step_on_price"] = {"ms_per_step": mse, "value": P * N / (mse * 1e-3),
                                                 "price": float(oe[0].cpu().numpy().ravel()[0])}
+        msec, oec = timed(max(3, args.steps // 2), scheme="euler_x", adjoint="checkpoint")
+        variants["fp32_euler_step_on_price_checkpoint"] = {
+            "ms_per_step": msec, "value": P * N / (msec * 1e-3),
+            "max_bucket_err_vs_stored": float(np.abs(oec[2].cpu().numpy() - oe[2].cpu().numpy()).max()
+                                              / np.abs(oe[2].cpu().numpy()).max())}
         # the TPU runs' mixed precision held sigma in bfloat16 for the interpolation
         # (Sec. IV-D); the same rounding of the nodes here, with its effect on the
         # estimates next to FP32's own distance from FP64 on the same paths

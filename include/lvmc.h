@@ -127,9 +127,8 @@ typedef struct {
     int32_t scheme;         /* LV_SCHEME_LOG_EULER (default): the explicit Euler step on
                                y = ln(X/X0) with the Ito drift -sigma^2/2; LV_SCHEME_EULER_X: the
                                explicit Euler step on X itself, X += sigma(X, t) X sqrt(dt) Z, as
-                               Sec. IV-A narrates the scheme (stored and price-only adjoint modes;
-                               LV_ERR_UNSUPPORTED with LV_ADJ_CHECKPOINT).  The split calls
-                               lv_forward_dev / lv_backward_dev step log-Euler. */
+                               Sec. IV-A narrates the scheme, in every adjoint mode.  The split
+                               calls lv_forward_dev / lv_backward_dev step log-Euler. */
     int32_t sigma_bf16;     /* 1: round every node of sigma to bfloat16 (FP64 -> FP32 -> bfloat16,
                                each to nearest with ties to even) before the vol table is built:
                                the precision in which the paper's mixed-precision TPU runs hold

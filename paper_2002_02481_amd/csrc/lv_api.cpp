@@ -309,8 +309,6 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     if (o.adjoint == LV_ADJ_DEFAULT) o.adjoint = LV_ADJ_STORED;
     if (o.scheme != LV_SCHEME_LOG_EULER && o.scheme != LV_SCHEME_EULER_X)
         return fail(ctx, LV_ERR_ARG, "unknown scheme %d", o.scheme);
-    if (o.scheme == LV_SCHEME_EULER_X && o.adjoint == LV_ADJ_CHECKPOINT)
-        return fail(ctx, LV_ERR_UNSUPPORTED, "the Euler step on X runs with the stored or no adjoint");
     if (o.sigma_bf16 != 0 && o.sigma_bf16 != 1) return fail(ctx, LV_ERR_ARG, "sigma_bf16 must be 0 or 1");
     if (o.ckpt_every == 0) o.ckpt_every = 16;
     if (o.ckpt_every != 8 && o.ckpt_every != 16 && o.ckpt_every != 32)

@@ -801,9 +801,11 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
 // Checkpoints live in per-block slots reused by every tile of the block.  The
 // LDS table holds one segment; consecutive uses of the same segment (the last
 // one forward then backward, the first one backward then forward for the next
-// tile) share its copy.
+// tile) share its copy.  EX: the Euler step on X; the checkpoints hold X, and the
+// re-simulated segment keeps c_n = X_n sqrt(dt) Z_n (the derivative of X_{n+1} in
+// sigma_n) with d X_{n+1} / d X_n = 1 + c_n (sigma_n / X_n + d sigma / d X).
 // --------------------------------------------------------------------------
-template <typename R, int AXIS, int SEG, bool MAGIC>
+template <typename R, int AXIS, int SEG, bool MAGIC, bool EX>
 __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -826,7 +828,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     constexpr bool magic = MAGIC;   // the launcher chose it: qmax <= Math<R>::MAGIC_MAX
     const double scd = ldexp(1.0, F), inv_sc = ldexp(1.0, -F);
     const R sdt = (R)a.sqrt_dt, hdt = (R)(0.5 * a.dt), inv_du = (R)a.inv_du, a_off = (R)a.a_off;
-    const R spot = (R)a.spot, amax = (R)(I - 1);
+    const R spot = (R)a.spot, amax = (R)(I - 1), inv_spot = (R)(1.0 / a.spot);
     const int n_seg = (N + SEG - 1) / SEG, KI1 = a.K * (I + 1);
     Acc *Hl = H + (tid % a.K) * (I + 1);   // this lane's copy of a histogram row
     R *CK = (R *)a.ckpt;
@@ -840,7 +842,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         const bool active = p < a.P;
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         // ---- forward: checkpoints and payoff sums
-        R y = 0;
+        R y = EX ? spot : (R)0;
         int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
@@ -864,11 +866,12 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     for (int r = 0; r < 4; ++r) {
                         const int n = n0 + r;
                         if (n < N) {
-                            const Look<R> L = lookup<R, AXIS>(y, tab + 2 * (4 * q4 + r) * I, inv_du,
-                                                              a_off, amax, spot);
-                            y = fma(L.s, fma(-hdt, L.s, z[r]), y);
+                            const Look<R> L = lookup_state<R, AXIS, EX>(y, tab + 2 * (4 * q4 + r) * I,
+                                                                        inv_du, a_off, inv_spot, amax, spot);
+                            if (EX) y = fma(L.s * y, z[r], y);
+                            else y = fma(L.s, fma(-hdt, L.s, z[r]), y);
                             if (n + 1 == next_tap) {
-                                fwd_payoffs<R, false>(a, tap, y, active, wpart, wave, lane);
+                                fwd_payoffs<R, EX>(a, tap, y, active, wpart, wave, lane);
                                 ++tap;
                                 next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
                             }
@@ -910,11 +913,16 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     for (int r = 0; r < 4; ++r) {
                         const int k = 4 * q4 + r;
                         if (n0 + r < N) {
-                            const Look<R> L = lookup<R, AXIS>(yy, tab + 2 * k * I, inv_du, a_off,
-                                                              amax, spot);
+                            const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
+                                                                        inv_spot, amax, spot);
                             ys[k] = yy;
-                            cs[k] = fma((R)-2 * hdt, L.s, z[r]);
-                            yy = fma(L.s, fma(-hdt, L.s, z[r]), yy);
+                            if (EX) {
+                                cs[k] = yy * z[r];
+                                yy = fma(L.s, cs[k], yy);
+                            } else {
+                                cs[k] = fma((R)-2 * hdt, L.s, z[r]);
+                                yy = fma(L.s, fma(-hdt, L.s, z[r]), yy);
+                            }
                         }
                     }
                 }
@@ -928,10 +936,12 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 for (int r = 0; r < 4; ++r) {
                     const int k = 4 * q4 + r;
                     if (na + k < N) {
-                        L[r] = lookup<R, AXIS>(ys[k], tab + 2 * k * I, inv_du, a_off, amax, spot);
+                        L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off, inv_spot,
+                                                         amax, spot);
                         R d = L[r].in ? L[r].d * inv_du : (R)0;
                         if (AXIS == 0) d *= L[r].S;
-                        dsd[r] = d;
+                        // EX: sigma / X + d sigma / d X (on a log axis d sigma / d X = (d / du) / X)
+                        dsd[r] = EX ? (L[r].s + d) * Math<R>::rcp(ys[k]) : d;
                     }
                 }
 #pragma unroll
@@ -940,7 +950,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     const int n = na + k;
                     if (n < N) {
                         if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R, false>(a, rtap, y_next, lam, scd);
+                            lam = rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
                             if (!active) lam = 0;
                             --rtap;
                             cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
@@ -955,7 +965,8 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         }
         __syncthreads();
         fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
-        const double l0 = wave_sum(active ? (double)lam * inv_sc : 0.0);
+        // the adjoint of y_0 = ln(X_0 / spot): with EX, lambda is that of X_0 = spot
+        const double l0 = wave_sum(active ? (double)lam * inv_sc * (EX ? a.spot : 1.0) : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
     __syncthreads();
@@ -1179,8 +1190,13 @@ hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipSt
 template <typename R, int SEG, bool MAGIC>
 static void fused_seg(const Args &a, int blocks, int block, hipStream_t st, Ev ev) {
     const size_t lds = lds_of<R>(FUSED_CKPT, a, block, SEG);
-    if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG, MAGIC>), blocks, block, lds, st, a);
-    else LAUNCH((k_fused<R, 1, SEG, MAGIC>), blocks, block, lds, st, a);
+    if (a.scheme == 1) {
+        if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG, MAGIC, true>), blocks, block, lds, st, a);
+        else LAUNCH((k_fused<R, 1, SEG, MAGIC, true>), blocks, block, lds, st, a);
+    } else {
+        if (a.axis == 0) LAUNCH((k_fused<R, 0, SEG, MAGIC, false>), blocks, block, lds, st, a);
+        else LAUNCH((k_fused<R, 1, SEG, MAGIC, false>), blocks, block, lds, st, a);
+    }
 }
 
 template <typename R, bool MAGIC>

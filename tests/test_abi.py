@@ -138,12 +138,12 @@ def test_planned_histogram_window_fits_lds():
 
 
 def test_check_scheme_options():
-    """The Euler step on X is planned for the stored and price-only modes; an unknown
-    scheme is an argument error and checkpoints with it are refused."""
-    assert lv.check(**_req(), scheme="euler_x") == _lib.LV_OK
-    assert lv.check(**_req(), scheme="euler_x", adjoint="none") == _lib.LV_OK
+    """The Euler step on X is planned in every adjoint mode; an unknown scheme is an
+    argument error."""
+    for adj in ("stored", "checkpoint", "none"):
+        assert lv.check(**_req(), scheme="euler_x", adjoint=adj) == _lib.LV_OK
     assert lv.check(**_req(), scheme=7) == _lib.LV_ERR_ARG
-    assert lv.check(**_req(), scheme="euler_x", adjoint="checkpoint") == _lib.LV_ERR_UNSUPPORTED
+    assert lv.check(**_req(), scheme=-1) == _lib.LV_ERR_ARG
 
 
 def test_check_sigma_bf16_option():

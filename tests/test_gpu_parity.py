@@ -223,11 +223,22 @@ def test_sigma_bf16(lv, ctx, orc, precision):
             assert np.array_equal(g["price"], want["price"]) and np.array_equal(g["grad"], want["grad"])
 
 
-def test_euler_x_refuses_checkpoints(lv, ctx):
-    wl = W.small_call()
-    with pytest.raises(lv.LVError, match="UNSUPPORTED"):
-        gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, precision=32, scheme="euler_x",
-                adjoint="checkpoint")
+@pytest.mark.parametrize("precision,axis,seg", [(32, "lin", 16), (64, "lin", 8), (32, "log", 32),
+                                               (64, "log", 16)])
+def test_euler_x_checkpoint(lv, ctx, orc, precision, axis, seg):
+    """The Euler step on X with the checkpointed adjoint (each segment re-simulated from
+    its checkpoint and the Philox counters) against the oracle's scheme 1, on both axis
+    kinds and every segment length; the same workloads as the stored-state test."""
+    if axis == "lin":
+        wl = W.small_call()
+        surf, book, P, N, seed = wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed
+    else:
+        surf, book, P, N, seed = W.book_surface(0), mixed_book(), 20000 + 37, 156, 3
+    s = surf.rounded_to_f32() if precision == 32 else surf
+    ref = orc.price_and_grad(s, book, P, N, seed=seed, scheme=1)
+    got = gpu_run(lv, ctx, surf, book, P, N, seed, precision=precision, scheme="euler_x",
+                  adjoint="checkpoint", ckpt_every=seg)
+    assert_parity(got, ref, precision, f"euler_x checkpoint {axis} {precision} seg {seg}")
 
 
 @pytest.mark.parametrize("P,N", [(2, 1), (3, 2), (1000, 13), (257, 5)])
