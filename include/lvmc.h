@@ -118,9 +118,10 @@ typedef struct {
     int32_t fwd_block;      /* threads per block of the separate forward kernel (stored and
                                price-only paths); 0 = tuned default */
     int32_t fwd_blocks_per_cu; /* persistent blocks per CU of that forward kernel; 0 = default */
-    int32_t dense_adjoint;  /* stored adjoint: 1 = sweep every path back; 0 (default) = sweep only
-                               the paths with an option in the money at its maturity, since every
-                               other path has a zero adjoint and contributes exactly nothing */
+    int32_t dense_adjoint;  /* stored and checkpointed adjoints: 1 = sweep every path back;
+                               0 (default) = sweep only the paths with an option of nonzero
+                               cotangent in the money at its maturity, since every other path
+                               has a zero adjoint and contributes exactly nothing */
     int32_t profile_kinds;  /* with profile: bit (1 << LV_K_*) set = time that kernel kind; 0 = all.
                                A timed dispatch waits for its timestamp (several microseconds),
                                so timing only the kernel of interest keeps the others' pace */

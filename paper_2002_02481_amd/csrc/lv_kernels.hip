@@ -162,7 +162,7 @@ __device__ __forceinline__ T ldu(const T *p) {
 // LDS carve-up, shared by the kernels and the host planner.
 // --------------------------------------------------------------------------
 struct Lds {
-    size_t g64, wpart, wlam, tab, hist, live, total;
+    size_t g64, wpart, wlam, tab, hist, live, yfin, total;
 };
 
 // CH: path tiles per live-path list of the stored reverse kernel.
@@ -183,8 +183,12 @@ __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes,
     off += align16((size_t)tab_bufs * W * I * 2 * rbytes);
     L.hist = off;
     off += grad ? align16((size_t)WH * K * (I + 1) * accbytes) : 0;   // rows of I + 1 words
-    L.live = off;
-    off += variant == REV_STORED ? align16(((size_t)CH * wpb * 64 + 16) * 4) : 0;   // list + wave counts
+    L.live = off;   // live-path list + wave counts
+    off += variant == REV_STORED   ? align16(((size_t)CH * wpb * 64 + 16) * 4)
+           : variant == FUSED_CKPT ? align16(((size_t)wpb * 64 + 16) * 4)
+                                   : 0;
+    L.yfin = off;   // the fused kernel's final state per lane
+    off += variant == FUSED_CKPT ? align16((size_t)wpb * 64 * rbytes) : 0;
     L.total = off;
     return L;
 }
@@ -578,19 +582,22 @@ constexpr int RB = 8;
 // A path for which this fails has lambda = 0 at every step and contributes exactly
 // nothing to the gradient or to delta.
 template <typename R, bool EX>
-__device__ bool path_live(const Args &a, const R *Y, size_t P, size_t p) {
-    for (int t = 0; t < a.n_taps; ++t) {
-        const int n = a.tap_step[t];
-        const R y = Y[(size_t)(n - 1) * P + p];
-        const double Sd = EX ? (double)y : (double)((R)a.spot * Math<R>::ex(y));
-        const int k0 = ldu(a.tap_first + t), kc = ldu(a.tap_count + t);
-        for (int q = 0; q < kc; ++q) {
-            const int k = k0 + q;
-            if (ldu(a.cot + ldu(a.opt_orig + k)) == 0.0) continue;
-            const double K = ldu(a.opt_strike + k);
-            if (ldu(a.opt_put + k) ? (Sd < K) : (Sd > K)) return true;
-        }
+__device__ __forceinline__ bool tap_live(const Args &a, int t, R y) {
+    const double Sd = EX ? (double)y : (double)((R)a.spot * Math<R>::ex(y));
+    const int k0 = ldu(a.tap_first + t), kc = ldu(a.tap_count + t);
+    for (int q = 0; q < kc; ++q) {
+        const int k = k0 + q;
+        if (ldu(a.cot + ldu(a.opt_orig + k)) == 0.0) continue;
+        const double K = ldu(a.opt_strike + k);
+        if (ldu(a.opt_put + k) ? (Sd < K) : (Sd > K)) return true;
     }
+    return false;
+}
+
+template <typename R, bool EX>
+__device__ bool path_live(const Args &a, const R *Y, size_t P, size_t p) {
+    for (int t = 0; t < a.n_taps; ++t)
+        if (tap_live<R, EX>(a, t, Y[(size_t)(a.tap_step[t] - 1) * P + p])) return true;
     return false;
 }
 
@@ -801,7 +808,12 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
 // Checkpoints live in per-block slots reused by every tile of the block.  The
 // LDS table holds one segment; consecutive uses of the same segment (the last
 // one forward then backward, the first one backward then forward for the next
-// tile) share its copy.  EX: the Euler step on X; the checkpoints hold X, and the
+// tile) share its copy.  Only the tile's live paths (an option with a nonzero
+// cotangent in the money at its maturity, as in the stored reverse kernel; every
+// path with a.dense) are swept back: they are listed in lane order and taken by the
+// first lanes, so the waves beyond them skip the re-simulation and the sweep.  A lane
+// then reads another lane's checkpoints, which the block barrier makes visible.
+// EX: the Euler step on X; the checkpoints hold X, and the
 // re-simulated segment keeps c_n = X_n sqrt(dt) Z_n (the derivative of X_{n+1} in
 // sigma_n) with d X_{n+1} / d X_n = 1 + c_n (sigma_n / X_n + d sigma / d X).
 // --------------------------------------------------------------------------
@@ -817,6 +829,9 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     double *wlam = (double *)(smem + lay.wlam);
     R *tab = (R *)(smem + lay.tab);
     Acc *H = (Acc *)(smem + lay.hist);
+    int *list = (int *)(smem + lay.live);   // live lanes of the tile, in lane order
+    int *wcnt = list + blockDim.x;          // per-wave live counts
+    R *yfin = (R *)(smem + lay.yfin);       // each lane's state at the last step
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
@@ -843,6 +858,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         // ---- forward: checkpoints and payoff sums
         R y = EX ? spot : (R)0;
+        bool lv = false;
         int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
@@ -872,6 +888,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                             else y = fma(L.s, fma(-hdt, L.s, z[r]), y);
                             if (n + 1 == next_tap) {
                                 fwd_payoffs<R, EX>(a, tap, y, active, wpart, wave, lane);
+                                if (!lv) lv = tap_live<R, EX>(a, tap, y);
                                 ++tap;
                                 next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
                             }
@@ -880,8 +897,28 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 }
             }
         }
+        // ---- live lanes: lane t < n_live sweeps the path of lane list[t]
+        const bool live = active && (a.dense || lv);
+        const unsigned long long m = __ballot(live);
+        if (lane == 0) wcnt[wave] = __popcll(m);
+        yfin[tid] = y;
+        __syncthreads();   // also makes every lane's checkpoints visible to the block
+        int woff = 0, n_live = 0;
+        for (int v = 0; v < wpb; ++v) {
+            const int c = wcnt[v];
+            woff += v < wave ? c : 0;
+            n_live += c;
+        }
+        if (live) list[woff + __popcll(m & ((1ull << lane) - 1))] = tid;
+        __syncthreads();
+        const bool on = tid < n_live;
+        const bool wave_on = wave * 64 < n_live;
+        const int src = on ? list[tid] : tid;
+        const long long ps = (long long)tile * blockDim.x + src;
+        const uint32_t slo = (uint32_t)ps, shi = (uint32_t)((unsigned long long)ps >> 32);
+        const size_t sslot = (size_t)blockIdx.x * blockDim.x + src;
         // ---- reverse, segment by segment (lam is the adjoint of y times 2^F)
-        R lam = 0, y_next = y;
+        R lam = 0, y_next = yfin[src];
         int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
@@ -898,14 +935,15 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 __syncthreads();
                 tcur = sg;
             }
+            if (!wave_on) continue;   // no live path in this wave (the barriers above are the block's)
             const int hb = na - hcur * WH;   // histogram row of the segment's first step
             R ys[SEG], cs[SEG];
-            R yy = CK[(size_t)sg * slot_stride + slot];
+            R yy = CK[(size_t)sg * slot_stride + sslot];
 #pragma unroll
             for (int q4 = 0; q4 < SEG / 4; ++q4) {
                 const int n0 = na + 4 * q4;
                 if (n0 < N) {
-                    const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
+                    const Words w = philox10((uint32_t)(n0 >> 2), 0u, slo, shi, a.key0, a.key1);
                     R z[4];
                     Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
                     Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
@@ -916,9 +954,11 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                             const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
                                                                         inv_spot, amax, spot);
                             ys[k] = yy;
+                            // the forward's own arithmetic, so the re-simulated states (and
+                            // with them the seed tests) are the forward's bit for bit
                             if (EX) {
                                 cs[k] = yy * z[r];
-                                yy = fma(L.s, cs[k], yy);
+                                yy = fma(L.s * yy, z[r], yy);
                             } else {
                                 cs[k] = fma((R)-2 * hdt, L.s, z[r]);
                                 yy = fma(L.s, fma(-hdt, L.s, z[r]), yy);
@@ -951,7 +991,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     if (n < N) {
                         if (n + 1 == cur_tap) {
                             lam = rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
-                            if (!active) lam = 0;
+                            if (!on) lam = 0;
                             --rtap;
                             cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
                         }
@@ -966,7 +1006,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         __syncthreads();
         fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
         // the adjoint of y_0 = ln(X_0 / spot): with EX, lambda is that of X_0 = spot
-        const double l0 = wave_sum(active ? (double)lam * inv_sc * (EX ? a.spot : 1.0) : 0.0);
+        const double l0 = wave_sum(on ? (double)lam * inv_sc * (EX ? a.spot : 1.0) : 0.0);
         if (lane == 0) wlam[wave] += l0;
     }
     __syncthreads();

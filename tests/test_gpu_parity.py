@@ -267,12 +267,15 @@ def test_zero_buckets_exact(lv, ctx, orc):
         assert_parity(got, ref, precision, f"zero buckets {precision}")
 
 
-def test_live_path_sweep_matches_dense(lv, ctx):
-    """The stored reverse sweep visits only paths with an option in the money at its
-    maturity (every other path has a zero adjoint); sweeping every path instead
-    gives the same gradient and delta up to FP64 summation order, and the same
-    prices.  A single call (about half its paths are dead) and a 64-option book
-    whose cotangents are zero for every third option."""
+@pytest.mark.parametrize("adjoint,scheme", [("stored", "log_euler"), ("checkpoint", "log_euler"),
+                                            ("checkpoint", "euler_x")])
+def test_live_path_sweep_matches_dense(lv, ctx, adjoint, scheme):
+    """The reverse sweeps visit only paths with an option in the money at its maturity
+    (every other path has a zero adjoint): the stored kernel over lists of several
+    tiles, the checkpointed kernel per tile, its live paths taken by the first lanes.
+    Sweeping every path instead gives the same gradient and delta up to FP64 summation
+    order, and the same prices.  A single call (about half its paths are dead) and a
+    64-option book whose cotangents are zero for every third option."""
     small = W.small_call()
     b = W.book64()
     w = np.where(np.arange(b.n) % 3 == 0, 0.0, b.weight)
@@ -280,8 +283,9 @@ def test_live_path_sweep_matches_dense(lv, ctx):
              (W.book_surface(0), W.Book(b.is_put, b.strike, b.maturity, w), 1 << 15, 156)]
     for surf, bk, P, N in cases:
         for precision in (32, 64):
-            sp = gpu_run(lv, ctx, surf, bk, P, N, 3, precision=precision)
-            de = gpu_run(lv, ctx, surf, bk, P, N, 3, precision=precision, dense_adjoint=True)
+            sp = gpu_run(lv, ctx, surf, bk, P, N, 3, precision=precision, adjoint=adjoint, scheme=scheme)
+            de = gpu_run(lv, ctx, surf, bk, P, N, 3, precision=precision, adjoint=adjoint, scheme=scheme,
+                         dense_adjoint=True)
             assert np.array_equal(sp["price"], de["price"])
             gmax = np.abs(de["grad"]).max()
             dg = np.abs(sp["grad"] - de["grad"]).max()
