@@ -138,13 +138,14 @@ int floor_pow2(long long x) {
 // fused kernel.
 int table_window(const Plan &pl, const Shape &sh) { return pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W; }
 
-// Path tiles per live-path list of the stored reverse kernel: all of a block's
-// tiles, up to 4.
+// Path tiles per live-path list of the reverse kernels: all of a block's tiles, up
+// to 4 (stored states) or 2 (checkpoints: each tile of a list holds its own
+// checkpoint slots and its final states in LDS).
 int chunk_tiles(const Plan &pl, const Shape &sh, int n_cu) {
-    if (pl.adjoint == LV_ADJ_CHECKPOINT) return 1;
     const long long tiles = (pl.P + sh.block - 1) / sh.block;
     const long long blocks = std::min<long long>(tiles, (long long)n_cu * sh.bpc);
-    return (int)std::max<long long>(1, std::min<long long>(4, (tiles + blocks - 1) / blocks));
+    const long long cap = pl.adjoint == LV_ADJ_CHECKPOINT ? 2 : 4;
+    return (int)std::max<long long>(1, std::min<long long>(cap, (tiles + blocks - 1) / blocks));
 }
 
 size_t lds_adj(const Plan &pl, const Shape &sh, int WH, int n_cu) {
@@ -548,7 +549,7 @@ lv_status ensure_workspace(lv_ctx *ctx, const Plan &pl, bool adjoint) {
     }
     if (adjoint && pl.adjoint == LV_ADJ_CHECKPOINT) {
         const size_t nseg = (pl.N + pl.seg - 1) / pl.seg;
-        const size_t b = nseg * (size_t)pl.blocks * pl.block * real_bytes(pl.precision);
+        const size_t b = nseg * (size_t)pl.CH * pl.blocks * pl.block * real_bytes(pl.precision);
         if ((st = ensure(ctx, ctx->ckpt, b)) != LV_OK) return st;
     }
     return LV_OK;
@@ -687,7 +688,8 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
                   double *deltas);
 
 // Time one launch shape on the first surface: one untimed run (allocations,
-// first touch), then two timed runs.
+// first touch), then the fastest of three timed pairs of runs (a pair that a clock
+// change or another process slowed does not count).
 lv_status time_shape(lv_ctx *ctx, const Plan &pl, const Shape &c, const double *sigmas_dev, bool adjoint,
                      double *prices, double *stderrs, double *grads, double *deltas, hipEvent_t e0,
                      hipEvent_t e1, float *ms) {
@@ -697,14 +699,19 @@ lv_status time_shape(lv_ctx *ctx, const Plan &pl, const Shape &c, const double *
     lv_status st = apply_shape(ctx, q, c, ctx->n_cu, ctx->max_lds, false, false);
     if (st != LV_OK) return st;
     if ((st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas)) != LV_OK) return st;
-    hipError_t e = hipEventRecord(e0, ctx->stream());
-    for (int r = 0; r < 2 && st == LV_OK; ++r)
-        st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas);
-    if (st != LV_OK) return st;
-    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream());
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
-    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+    *ms = 1e30f;
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = hipEventRecord(e0, ctx->stream());
+        for (int r = 0; r < 2 && st == LV_OK; ++r)
+            st = run_dev(ctx, q, 1, sigmas_dev, adjoint, false, prices, stderrs, grads, deltas);
+        if (st != LV_OK) return st;
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream());
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+        *ms = std::min(*ms, t);
+    }
     return LV_OK;
 }
 
@@ -716,8 +723,9 @@ bool user_allows(const Plan &pl, const Shape &c) {
 
 // Autotuner: the separate forward kernel's shape first (stored and price-only
 // paths), then the adjoint (or fused) kernel's shape with that forward; each
-// candidate is timed on the first surface and the fastest kept per context and
-// request shape.
+// candidate is timed on the first surface in two sweeps over the candidates (the
+// first ones of a cold GPU run before its clocks have risen) and the fastest kept
+// per context and request shape.
 lv_status autotune(lv_ctx *ctx, Plan &pl, const double *sigmas_dev, bool adjoint, double *prices,
                    double *stderrs, double *grads, double *deltas) {
     const std::string key = tune_key(pl, adjoint);
@@ -733,18 +741,22 @@ lv_status autotune(lv_ctx *ctx, Plan &pl, const double *sigmas_dev, bool adjoint
             if (phase == 0 && (!adjoint || pl.adjoint == LV_ADJ_STORED))
                 cands = forward_candidates(pl, best, ctx->n_cu, ctx->max_lds);
             if (phase == 1 && adjoint) cands = adjoint_candidates(pl, best, ctx->n_cu, ctx->max_lds);
-            float best_ms = 1e30f;
-            for (const Shape &c : cands) {
-                if (!user_allows(pl, c)) continue;
-                float ms = 0.f;
-                if ((st = time_shape(ctx, pl, c, sigmas_dev, adjoint, prices, stderrs, grads, deltas, e0, e1,
-                                     &ms)) != LV_OK)
-                    break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = c;
+            std::vector<float> t(cands.size(), 1e30f);
+            for (int sweep = 0; sweep < 2 && st == LV_OK; ++sweep)
+                for (size_t i = 0; i < cands.size(); ++i) {
+                    if (!user_allows(pl, cands[i])) continue;
+                    float ms = 0.f;
+                    if ((st = time_shape(ctx, pl, cands[i], sigmas_dev, adjoint, prices, stderrs, grads, deltas,
+                                         e0, e1, &ms)) != LV_OK)
+                        break;
+                    t[i] = std::min(t[i], ms);
                 }
-            }
+            float best_ms = 1e30f;
+            for (size_t i = 0; i < cands.size() && st == LV_OK; ++i)
+                if (t[i] < best_ms) {
+                    best_ms = t[i];
+                    best = cands[i];
+                }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

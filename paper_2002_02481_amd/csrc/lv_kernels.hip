@@ -185,10 +185,10 @@ __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes,
     off += grad ? align16((size_t)WH * K * (I + 1) * accbytes) : 0;   // rows of I + 1 words
     L.live = off;   // live-path list + wave counts
     off += variant == REV_STORED   ? align16(((size_t)CH * wpb * 64 + 16) * 4)
-           : variant == FUSED_CKPT ? align16(((size_t)wpb * 64 + 16) * 4)
+           : variant == FUSED_CKPT ? align16(((size_t)CH * wpb * 64 + 16) * 4)
                                    : 0;
-    L.yfin = off;   // the fused kernel's final state per lane
-    off += variant == FUSED_CKPT ? align16((size_t)wpb * 64 * rbytes) : 0;
+    L.yfin = off;   // the fused kernel's final state per path of a chunk
+    off += variant == FUSED_CKPT ? align16((size_t)CH * wpb * 64 * rbytes) : 0;
     L.total = off;
     return L;
 }
@@ -808,11 +808,13 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_rev(Args a) {
 // Checkpoints live in per-block slots reused by every tile of the block.  The
 // LDS table holds one segment; consecutive uses of the same segment (the last
 // one forward then backward, the first one backward then forward for the next
-// tile) share its copy.  Only the tile's live paths (an option with a nonzero
-// cotangent in the money at its maturity, as in the stored reverse kernel; every
-// path with a.dense) are swept back: they are listed in lane order and taken by the
-// first lanes, so the waves beyond them skip the re-simulation and the sweep.  A lane
-// then reads another lane's checkpoints, which the block barrier makes visible.
+// tile) share its copy.  The block's tiles b, b + B, ... are taken CH at a time:
+// each is run forward into its own checkpoint slots, then only their live paths (an
+// option with a nonzero cotangent in the money at its maturity, as in the stored
+// reverse kernel; every path with a.dense) are swept back, listed in path order and
+// taken in passes of blockDim lanes, so waves beyond the list skip the re-simulation
+// and the sweep.  A lane then reads another lane's checkpoints, which the block
+// barrier makes visible.
 // EX: the Euler step on X; the checkpoints hold X, and the
 // re-simulated segment keeps c_n = X_n sqrt(dt) Z_n (the derivative of X_{n+1} in
 // sigma_n) with d X_{n+1} / d X_n = 1 + c_n (sigma_n / X_n + d sigma / d X).
@@ -829,9 +831,10 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     double *wlam = (double *)(smem + lay.wlam);
     R *tab = (R *)(smem + lay.tab);
     Acc *H = (Acc *)(smem + lay.hist);
-    int *list = (int *)(smem + lay.live);   // live lanes of the tile, in lane order
-    int *wcnt = list + blockDim.x;          // per-wave live counts
-    R *yfin = (R *)(smem + lay.yfin);       // each lane's state at the last step
+    const int CH = a.CH, T = blockDim.x, B = gridDim.x;
+    int *list = (int *)(smem + lay.live);   // live paths of a chunk, as tile-in-chunk * T + lane
+    int *wcnt = list + CH * T;              // per-wave live counts
+    R *yfin = (R *)(smem + lay.yfin);       // state at the last step, per path of the chunk
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
@@ -852,17 +855,20 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     TabStage<R> stg;
     int tcur = -1;   // segment whose table is in LDS
 
-    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-        const long long p = (long long)tile * blockDim.x + tid;
+    for (int c0 = blockIdx.x; c0 < a.n_tiles; c0 += CH * B) {
+      int n_live = 0;
+      for (int kt = 0; kt < CH && c0 + kt * B < a.n_tiles; ++kt) {
+        const int tile = c0 + kt * B;
+        const long long p = (long long)tile * T + tid;
         const bool active = p < a.P;
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
-        // ---- forward: checkpoints and payoff sums
+        // ---- forward: checkpoints (slot set kt) and payoff sums
         R y = EX ? spot : (R)0;
         bool lv = false;
         int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
-            CK[(size_t)sg * slot_stride + slot] = y;
+            CK[(size_t)(sg * CH + kt) * slot_stride + slot] = y;
             if (sg != tcur) {
                 __syncthreads();
                 stg.issue(a, na, nw);
@@ -897,28 +903,33 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 }
             }
         }
-        // ---- live lanes: lane t < n_live sweeps the path of lane list[t]
+        // ---- list the tile's live paths after those of the chunk's earlier tiles
         const bool live = active && (a.dense || lv);
         const unsigned long long m = __ballot(live);
         if (lane == 0) wcnt[wave] = __popcll(m);
-        yfin[tid] = y;
+        yfin[kt * T + tid] = y;
         __syncthreads();   // also makes every lane's checkpoints visible to the block
-        int woff = 0, n_live = 0;
+        int woff = n_live, tot = 0;
         for (int v = 0; v < wpb; ++v) {
             const int c = wcnt[v];
             woff += v < wave ? c : 0;
-            n_live += c;
+            tot += c;
         }
-        if (live) list[woff + __popcll(m & ((1ull << lane) - 1))] = tid;
+        if (live) list[woff + __popcll(m & ((1ull << lane) - 1))] = kt * T + tid;
+        n_live += tot;
         __syncthreads();
-        const bool on = tid < n_live;
-        const bool wave_on = wave * 64 < n_live;
-        const int src = on ? list[tid] : tid;
-        const long long ps = (long long)tile * blockDim.x + src;
+      }
+      // ---- passes of T listed paths: lane t takes list entry base + t
+      for (int base = 0; base < n_live; base += T) {
+        const bool on = base + tid < n_live;
+        const bool wave_on = base + wave * 64 < n_live;
+        const int e = list[on ? base + tid : base];   // lanes past the list repeat a listed path
+        const int ek = e / T, src = e - ek * T;
+        const long long ps = (long long)(c0 + ek * B) * T + src;
         const uint32_t slo = (uint32_t)ps, shi = (uint32_t)((unsigned long long)ps >> 32);
-        const size_t sslot = (size_t)blockIdx.x * blockDim.x + src;
+        const size_t sslot = (size_t)ek * slot_stride + (size_t)blockIdx.x * T + src;
         // ---- reverse, segment by segment (lam is the adjoint of y times 2^F)
-        R lam = 0, y_next = yfin[src];
+        R lam = 0, y_next = yfin[e];
         int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
@@ -938,7 +949,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
             if (!wave_on) continue;   // no live path in this wave (the barriers above are the block's)
             const int hb = na - hcur * WH;   // histogram row of the segment's first step
             R ys[SEG], cs[SEG];
-            R yy = CK[(size_t)sg * slot_stride + sslot];
+            R yy = CK[(size_t)sg * CH * slot_stride + sslot];
 #pragma unroll
             for (int q4 = 0; q4 < SEG / 4; ++q4) {
                 const int n0 = na + 4 * q4;
@@ -1008,6 +1019,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         // the adjoint of y_0 = ln(X_0 / spot): with EX, lambda is that of X_0 = spot
         const double l0 = wave_sum(on ? (double)lam * inv_sc * (EX ? a.spot : 1.0) : 0.0);
         if (lane == 0) wlam[wave] += l0;
+      }
     }
     __syncthreads();
     double *out = a.part + (size_t)blockIdx.x * a.Q;

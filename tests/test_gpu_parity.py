@@ -296,6 +296,27 @@ def test_live_path_sweep_matches_dense(lv, ctx, adjoint, scheme):
             assert abs(sp["delta"] - de["delta"]) <= 1e-12 * abs(de["delta"])
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+def test_checkpoint_lists_span_tiles(lv, ctx, orc, precision):
+    """The checkpointed kernel with 64-lane blocks, one per CU, on 2^15 + 37 paths: 513
+    tiles, more than the blocks, so each block lists the live paths of two tiles at a
+    time (each tile with its own checkpoint slots) and the last, ragged tile alone.
+    Against the oracle, and bit-equal gradients to sweeping every path."""
+    wl = W.small_call()
+    P, N = (1 << 15) + 37, wl.n_steps
+    s = wl.surface.rounded_to_f32() if precision == 32 else wl.surface
+    ref = orc.price_and_grad(s, wl.book, P, N, seed=wl.seed)
+    shape = dict(adjoint="checkpoint", block=64, blocks_per_cu=1, precision=precision)
+    got = gpu_run(lv, ctx, wl.surface, wl.book, P, N, wl.seed, **shape)
+    info = ctx.run_info()
+    assert info["block"] == 64 and 513 > info["n_blocks"], info
+    assert_parity(got, ref, precision, f"checkpoint lists over tiles FP{precision}")
+    de = gpu_run(lv, ctx, wl.surface, wl.book, P, N, wl.seed, dense_adjoint=True, **shape)
+    assert np.array_equal(got["price"], de["price"])
+    assert np.abs(got["grad"] - de["grad"]).max() <= 1e-12 * np.abs(de["grad"]).max()
+    assert abs(got["delta"] - de["delta"]) <= 1e-12 * abs(de["delta"])
+
+
 def test_block_shapes_agree(lv, ctx, orc):
     """Every launch shape computes the same thing: block sizes, histogram copies,
     windows and grid sizes all pass the same parity bar."""
