@@ -143,6 +143,35 @@ def mixed_book():
                   [1.0, 2.0, -0.5, 1.5, 0.25])
 
 
+def max_book():
+    """256 options (the most a book may hold): maturities on every one of 52 weekly
+    steps, calls and puts, strikes 70..130, weights of both signs and some zero."""
+    k = np.arange(256)
+    w = np.where(k % 7 == 3, 0.0, np.cos(0.37 * k))
+    return W.Book((k % 3 == 1).astype(np.int32), 70.0 + 60.0 * ((k * 37) % 256) / 255.0,
+                  (1 + (k * 11) % 52) / 52.0, w)
+
+
+@pytest.mark.parametrize("precision,adjoint,block", [(32, "stored", 0), (32, "checkpoint", 0),
+                                                     (64, "stored", 0), (32, "stored", 256),
+                                                     (64, "checkpoint", 128)])
+def test_max_book(lv, ctx, orc, precision, adjoint, block):
+    """The largest book, 256 options tapped at 52 different steps, on 4096 + 13 paths
+    of the 21 x 13 grid: prices, standard errors, the grid of the weighted book and
+    delta against the oracle, with the default and with explicit block sizes (the
+    per-wave payoff sums then take most of the LDS).  257 options are refused."""
+    wl = W.small_call()
+    book = max_book()
+    P, N = 4096 + 13, 52
+    s = wl.surface.rounded_to_f32() if precision == 32 else wl.surface
+    ref = orc.price_and_grad(s, book, P, N, seed=7)
+    got = gpu_run(lv, ctx, wl.surface, book, P, N, 7, precision=precision, adjoint=adjoint, block=block)
+    assert_parity(got, ref, precision, f"256 options {precision} {adjoint} block {block}")
+    big = W.Book(np.zeros(257, np.int32), np.full(257, 100.0), np.full(257, 1.0), np.ones(257))
+    with pytest.raises(lv.LVError, match="UNSUPPORTED"):
+        gpu_run(lv, ctx, wl.surface, big, P, N, 7, precision=precision)
+
+
 @pytest.mark.parametrize("precision,adjoint", [(32, "stored"), (64, "stored"), (32, "checkpoint")])
 def test_book_log_axis_ragged(lv, ctx, orc, precision, adjoint):
     """Log-spaced 60 x 30 grid, calls and puts of uneven maturity with weights, a path
