@@ -155,3 +155,14 @@ def test_check_sigma_bf16_option():
     assert lv.check(**_req(), sigma_bf16=0) == _lib.LV_OK
     assert lv.check(**_req(), sigma_bf16=2) == _lib.LV_ERR_ARG
     assert lv.check(**_req(), sigma_bf16=-1) == _lib.LV_ERR_ARG
+
+
+def test_grid_larger_than_a_block_is_refused():
+    """A gradient grid that no block's LDS can hold (200 x 100 nodes) is refused by the
+    planner with LV_ERR_UNSUPPORTED in every mode; 150 x 80 plans."""
+    for (I, J), want in (((150, 80), _lib.LV_OK), ((200, 100), _lib.LV_ERR_UNSUPPORTED)):
+        sa, ta = W.Axis(I, W.LOG, 20.0, 400.0), W.Axis(J, W.LIN, 0.0, 2.0)
+        s = W.Surface(sa, ta, np.full((I, J), 0.2))
+        for prec in (32, 64):
+            for adj in ("stored", "checkpoint"):
+                assert lv.check(s, 100.0, [100.0], [2.0], 1 << 13, 104, precision=prec, adjoint=adj) == want
