@@ -4,11 +4,15 @@ axis, shown on the oracle itself (CPU only).
 Two copies of the oracle change only how the cell coordinate of a state is formed:
 one rounds the state y = ln(S/S0) to single precision and keeps the rest exact; the
 other forms the coordinate as the FP32 kernels do, one single-precision fused
-multiply-add with the reciprocal spacing and the offset rounded to single precision
-(nodes then sit a few 1e-6 cells off their places, and coordinates just below a node
-round onto it).  On the 150 x 80 grid only the second moves buckets by more than
-1e-5 of max|g|, by about the amount the GPU's FP32 kernels differ: the flips it causes
-fall on the same side on every path, so more paths do not average them away.
+multiply-add with the reciprocal spacing and the offset rounded to single precision,
+which moves coordinates by up to a few 1e-6 cells.  On the 150 x 80 grid (about 50
+nodes per unit of ln S, noisy nodes, so neighbouring cells have quite different
+slopes) the second copy flips a few states to the neighbouring cell; those paths then
+carry the other slope in their adjoint, and where such a path has a large adjoint a
+bucket moves by about 1.3e-4 of max|g|, the size of the GPU's FP32 difference on this
+grid and path count.  The first copy stays within 1e-5.  Which paths flip changes
+with the path count, so the largest bucket difference does not fall steadily as
+paths are added.
 """
 import os
 

@@ -187,11 +187,10 @@ def test_large_grid(lv, ctx, orc, precision, adjoint):
     launch.  FP32 bar: on this grid (about 50 nodes per unit of ln S) a few buckets
     differ by up to 1.4e-4 of max|g|, the same at 2^13 and 2^17 paths and the same for
     every block size, histogram scale and the checkpointed kernel, so it is the FP32
-    path arithmetic, not sampling or the accumulation: the FP32 cell coordinate puts
-    nodes a few 1e-6 cells off and rounds coordinates just below a node onto it, so
-    those states take the upper cell on every path (test_fp32_node_flips shows it on
-    the oracle).  Every bucket within 3e-4 of max|g|, and all but 1% within the usual
-    1e-4."""
+    path arithmetic, not the accumulation: the FP32 cell coordinate flips a few states
+    to the neighbouring cell, and on this noisy grid a flipped path with a large adjoint
+    moves a bucket that much (test_fp32_node_flips reproduces it on the oracle).  Every
+    bucket within 3e-4 of max|g|, and all but 1% within the usual 1e-4."""
     surf = large_grid()
     book = W.Book([0, 1], [100.0, 90.0], [2.0, 1.0], [1.0, 0.5])
     P, N = (1 << 17) + 5, 104
