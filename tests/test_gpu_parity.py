@@ -432,19 +432,27 @@ def test_surface_batch(lv, ctx, orc, precision):
             assert err.max() <= FLIP_GRAD_TOL * gmax
 
 
-def test_device_api_and_graph_replay(lv, ctx):
+@pytest.mark.parametrize("opts", [dict(), dict(adjoint="checkpoint"),
+                                  dict(adjoint="checkpoint", block=64, blocks_per_cu=1, n_paths=(1 << 15) + 37)],
+                         ids=["stored", "checkpoint", "checkpoint_lists_over_tiles"])
+def test_device_api_and_graph_replay(lv, ctx, opts):
+    """Graph replays equal the eager call bit for bit, with eager work of another shape
+    between replays: stored states, checkpoints, and checkpoints whose live-path lists
+    span two tiles."""
     import torch
     wl = W.small_call()
+    opts = dict(opts)
+    P = opts.pop("n_paths", wl.n_paths)
     sig = torch.tensor(wl.surface.sigma, dtype=torch.float64, device="cuda")
-    kw = dict(spot_axis=wl.surface.spot_axis, time_axis=wl.surface.time_axis, ctx=ctx)
-    say("  eager device call")
-    eager = lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], wl.n_paths, wl.n_steps, 0, **kw)
+    kw = dict(spot_axis=wl.surface.spot_axis, time_axis=wl.surface.time_axis, ctx=ctx, **opts)
+    say(f"  eager device call {opts}")
+    eager = lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], P, wl.n_steps, 0, **kw)
     eager = [t.clone() for t in eager]
     torch.cuda.synchronize()
     out = [torch.empty_like(t) for t in eager]
     for rep in range(3):
         say(f"  graph replay {rep}")
-        lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], wl.n_paths, wl.n_steps, 0, out=out,
+        lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], P, wl.n_steps, 0, out=out,
                               use_graph=True, **kw)
         torch.cuda.synchronize()
         assert ctx.run_info()["graph_replayed"] == (1 if rep > 0 else 0)
