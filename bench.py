@@ -315,6 +315,11 @@ def main():
             "fp32_vs_fp64_gpu_price_abs": float(abs(price32.ravel()[0] - p64.ravel()[0])),
             "fp32_vs_fp64_gpu_max_bucket_err_rel_maxg": float(np.abs(grad32 - g64).max() / np.abs(g64).max()),
             "price": float(price32.ravel()[0]), "stderr": float(se32.ravel()[0]),
+            # FP32's own error is far below the Monte Carlo error of the same paths, so at
+            # a fixed error both precisions need the same paths and the speed ratio is
+            # the ratio of step times
+            "fp32_error_over_stderr": float(abs(price32.ravel()[0] - p64.ravel()[0]) / se32.ravel()[0]),
+            "fp32_speedup_over_fp64_at_fixed_error": float(ms64 / ms_per_step),
         }
 
     gc.enable()
