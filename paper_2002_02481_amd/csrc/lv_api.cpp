@@ -128,9 +128,9 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // ---------------------------------------------------------------------------
 // Launch shapes
 // ---------------------------------------------------------------------------
-int floor_pow2(long long x) {
-    int p = 1;
-    while ((long long)p * 2 <= x) p *= 2;
+long long floor_pow2(long long x) {
+    long long p = 1;
+    while (p * 2 <= x) p *= 2;
     return p;
 }
 
@@ -180,6 +180,9 @@ int hist_window(const Plan &pl, const Shape &sh, size_t max_lds, int n_cu) {
     return (int)std::max<long long>(W, wh);
 }
 
+// Largest number of path tiles one launch takes (see apply_shape).
+constexpr long long kMaxTiles = (1ll << 30);
+
 // Defaults from launch-shape sweeps on MI355X: 1024-lane blocks with 2 histogram
 // copies and 32-step windows when there are enough paths for a block per CU;
 // smaller blocks for smaller problems so that every CU gets work.
@@ -191,6 +194,7 @@ Shape default_shape(const Plan &pl, int n_cu) {
     sh.W = 32;
     sh.bpc = 1;
     sh.fblock = (int)std::min<long long>(512, std::max<long long>(64, floor_pow2(pl.P / (2 * n_cu))));
+    if ((pl.P + sh.fblock - 1) / sh.fblock > kMaxTiles) sh.fblock = 1024;   // the largest path counts
     sh.fbpc = 4;
     return sh;
 }
@@ -217,14 +221,23 @@ lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds,
     if (lds_adj(pl, sh, pl.WH, n_cu) > max_lds)   // the window search keeps this; never launch past it
         return fail(ctx, LV_ERR_UNSUPPORTED, "planner: histogram window of %d steps needs %zu bytes of LDS (limit %zu)",
                     pl.WH, lds_adj(pl, sh, pl.WH, n_cu), max_lds);
+    // Tile counts are computed in 64 bits and must fit the kernels' int tile loops,
+    // whose counters run up to a tile count plus one stride of the grid (at most
+    // 4 tiles per list x 64 blocks per CU x the CUs), so they are capped well below 2^31.
+    const long long n_tiles = (pl.P + sh.block - 1) / sh.block;
+    const long long f_n_tiles = (pl.P + sh.fblock - 1) / sh.fblock;
+    if (n_tiles > kMaxTiles || f_n_tiles > kMaxTiles)
+        return fail(ctx, LV_ERR_UNSUPPORTED,
+                    "%lld paths need %lld tiles of %d (forward: %lld of %d); at most %lld tiles per launch",
+                    pl.P, n_tiles, sh.block, f_n_tiles, sh.fblock, kMaxTiles);
     pl.CH = chunk_tiles(pl, sh, n_cu);
     pl.bpc = sh.bpc;
-    pl.n_tiles = (int)((pl.P + pl.block - 1) / pl.block);
-    pl.blocks = (int)std::min<long long>(pl.n_tiles, (long long)n_cu * sh.bpc);
+    pl.n_tiles = (int)n_tiles;
+    pl.blocks = (int)std::min<long long>(n_tiles, (long long)n_cu * sh.bpc);
     pl.fblock = sh.fblock;
     pl.fbpc = sh.fbpc;
-    pl.f_n_tiles = (int)((pl.P + pl.fblock - 1) / pl.fblock);
-    pl.fblocks = (int)std::min<long long>(pl.f_n_tiles, (long long)n_cu * sh.fbpc);
+    pl.f_n_tiles = (int)f_n_tiles;
+    pl.fblocks = (int)std::min<long long>(f_n_tiles, (long long)n_cu * sh.fbpc);
     return LV_OK;
 }
 

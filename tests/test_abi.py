@@ -166,3 +166,34 @@ def test_grid_larger_than_a_block_is_refused():
         for prec in (32, 64):
             for adj in ("stored", "checkpoint"):
                 assert lv.check(s, 100.0, [100.0], [2.0], 1 << 13, 104, precision=prec, adjoint=adj) == want
+
+
+def test_tile_counts_fit_the_kernels():
+    """Path tiles are counted in 64 bits: a request whose tile count would not fit the
+    kernels' int tile loops is refused (2^38 + 320 paths in 64-lane blocks is 2^32 + 5
+    tiles, which an int cast would turn into 5), while 2^40 paths plan with the default
+    shapes (1024-lane blocks, 2^30 tiles) and one path more is an argument error."""
+    big = (1 << 38) + 320
+    assert lv.check(**_req(n_paths=big), block=64) == _lib.LV_ERR_UNSUPPORTED
+    assert b"tiles" in _lib.load().lv_last_error(None)
+    assert lv.check(**_req(n_paths=big), fwd_block=64) == _lib.LV_ERR_UNSUPPORTED
+    assert lv.check(**_req(n_paths=big)) == _lib.LV_OK
+    for adj in ("stored", "checkpoint", "none"):
+        assert lv.check(**_req(n_paths=1 << 40), adjoint=adj) == _lib.LV_OK
+    assert lv.check(**_req(n_paths=1 << 40), block=512) == _lib.LV_ERR_UNSUPPORTED
+    assert lv.check(**_req(n_paths=1 << 40), precision=64) == _lib.LV_ERR_UNSUPPORTED
+    assert lv.check(**_req(n_paths=(1 << 40) + 1)) == _lib.LV_ERR_ARG
+
+
+def test_create_without_a_device_is_a_hip_error(lib):
+    """With no HIP device (this runs on a host without a GPU) lv_create returns
+    LV_ERR_HIP, names the cause and leaves the out-pointer NULL; host-only calls keep
+    working afterwards."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present; the no-device path is checked on a host without one")
+    h = C.c_void_p(1)
+    assert lib.lv_create(C.byref(h), 0, None) == _lib.LV_ERR_HIP
+    assert h.value is None
+    assert b"device" in lib.lv_last_error(None)
+    assert lv.check(**_req()) == _lib.LV_OK
