@@ -186,6 +186,30 @@ lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf
                                 const lv_opts *opts, double *prices_dev, double *std_errs_dev,
                                 double *grads_dev, double *deltas_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lv_price_and_grad_dev
+ * with the same arguments and results, computed by the same kernels, but working
+ * only in a fixed per-GPU workspace of 64 MiB that the library holds from its
+ * load until the process ends; it calls no hipMalloc, hipFree or allocating
+ * library routine.  The caller still owns the inputs and outputs (device
+ * pointers as above).  The workspace holds the request's step and option tables,
+ * the per-step vol table, the per-block partial records and the stored states
+ * (LV_ADJ_STORED: n_steps x n_paths values) or the checkpoints (LV_ADJ_CHECKPOINT:
+ * a few segments per resident path, small); a request that needs more than 64 MiB
+ * returns LV_ERR_UNSUPPORTED before anything is launched, as do the same
+ * validation errors as lv_price_and_grad_dev.  use_graph, autotune and profile
+ * must be 0 (else LV_ERR_ARG); a launch shape this context has already tuned for
+ * the request (through lv_price_and_grad_dev with autotune) is used.  The tables
+ * are copied host to device on the context's stream.  Every call on one GPU uses
+ * that GPU's one workspace, which keeps the last call's contents: calls that
+ * overlap on one GPU (other streams, other contexts, other threads) race, so the
+ * caller serialises them.  Asynchronous on the context's stream. */
+lv_status lv_price_and_grad_noalloc(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
+                                    const double *sigmas_dev, double spot, const lv_book *book,
+                                    int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                    const lv_opts *opts, double *prices_dev, double *std_errs_dev,
+                                    double *grads_dev, double *deltas_dev);
+
 /* Bump-and-reprice: the vol-grid gradient by the finite differences the adjoint
  * replaces (arXiv 2002.02481, Sec. III: one simulation at p + eps/2, one at
  * p - eps/2, the difference over eps), for comparison with it.  For every node

@@ -22,7 +22,7 @@ from ._lib import ADJOINT, LVError, lv_axis, lv_book, lv_grid, lv_opts, lv_run_i
 
 __all__ = ["Context", "LVError", "price_and_grad", "price_and_grad_batch", "price_and_grad_dev",
            "forward_dev", "backward_dev", "states_bytes", "LVPrice", "check", "default_context",
-           "bump_grad_dev", "per_option_grads_dev"]
+           "bump_grad_dev", "per_option_grads_dev", "price_and_grad_noalloc"]
 
 
 def _lib_handle():
@@ -281,6 +281,35 @@ def price_and_grad_dev(sigmas, spot, strikes, maturities, n_paths, n_steps, seed
     else:
         prices, stderrs, grads, deltas = out
     st = ctx.lib.lv_price_and_grad_dev(
+        ctx.h, C.byref(grid), n_surf, _ptr(sigmas), float(spot), C.byref(book.c), int(n_paths),
+        int(n_steps), int(seed), C.byref(o), _ptr(prices), _ptr(stderrs), _ptr(grads), _ptr(deltas))
+    _check_status(st, ctx.h)
+    return prices, stderrs, grads, deltas
+
+
+def price_and_grad_noalloc(sigmas, spot, strikes, maturities, n_paths, n_steps, seed=0, *, spot_axis,
+                           time_axis, is_put=None, weights=None, want_grad=True, out,
+                           ctx: Optional[Context] = None, **opts):
+    """price_and_grad_dev through the allocation-free entry point: the library works in
+    its fixed per-GPU workspace and allocates nothing.  `out` = (prices, std_errs, grads,
+    deltas) CUDA float64 tensors the caller allocated (grads and deltas may be None)."""
+    import torch
+    ctx = ctx or default_context(sigmas.device.index or 0)
+    ctx.use_torch_stream()
+    if sigmas.dim() == 2:
+        sigmas = sigmas.unsqueeze(0)
+    assert sigmas.is_cuda and sigmas.dtype == torch.float64 and sigmas.is_contiguous()
+    n_surf = sigmas.shape[0]
+    grid = make_grid(spot_axis, time_axis)
+    book = _Book(strikes, maturities, is_put, weights)
+    o = make_opts(**opts)
+    prices, stderrs, grads, deltas = out
+    if not want_grad:
+        grads = deltas = None
+    for t in (prices, stderrs, grads, deltas):
+        assert t is None or (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous())
+    assert prices.numel() >= n_surf * book.n and stderrs.numel() >= n_surf * book.n
+    st = ctx.lib.lv_price_and_grad_noalloc(
         ctx.h, C.byref(grid), n_surf, _ptr(sigmas), float(spot), C.byref(book.c), int(n_paths),
         int(n_steps), int(seed), C.byref(o), _ptr(prices), _ptr(stderrs), _ptr(grads), _ptr(deltas))
     _check_status(st, ctx.h)

@@ -77,6 +77,8 @@ SIGNATURES = {
                                           _PO, _vp, _vp, _vp, _vp]),
     "lv_price_and_grad_dev": (C.c_int, [_vp, _PG, _i32, _vp, C.c_double, _PB, _i64, _i32, _u64,
                                         _PO, _vp, _vp, _vp, _vp]),
+    "lv_price_and_grad_noalloc": (C.c_int, [_vp, _PG, _i32, _vp, C.c_double, _PB, _i64, _i32, _u64,
+                                            _PO, _vp, _vp, _vp, _vp]),
     "lv_bump_grad_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _PO, C.c_double,
                                    _i32, _vp]),
     "lv_states_bytes": (C.c_int, [_i32, _i64, _i32, C.POINTER(C.c_size_t)]),

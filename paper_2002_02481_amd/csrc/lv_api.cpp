@@ -64,6 +64,9 @@ struct lv_ctx {
     std::vector<char> plan_bytes;     // what planbuf holds
     lv_run_info info{};
     int last_Q = 0, last_G = 0, last_nopt = 0;   // record layout of the last call's partials
+    const void *last_part = nullptr;             // where they are
+    void *scratch = nullptr;                     // this device's allocation-free workspace
+    std::vector<char> scratch_tables;            // host copy of the tables it last uploaded
     std::map<std::string, Shape> tuned;          // autotuner results per request shape
     bool last_autotuned = false;
     // kernel timing (lv_opts.profile)
@@ -468,9 +471,14 @@ void put(std::vector<char> &v, const std::vector<T> &x, size_t &off) {
     if (!x.empty()) std::memcpy(v.data() + off, x.data(), x.size() * sizeof(T));
 }
 
-lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
-    std::vector<char> v;
+// Byte offsets of the packed tables inside one buffer.
+struct TableOffsets {
     size_t o[10];
+};
+
+std::vector<char> pack_tables(const Plan &pl, TableOffsets &to) {
+    std::vector<char> v;
+    size_t *o = to.o;
     put(v, pl.tj, o[0]);
     put(v, pl.cell_lo, o[9]);
     put(v, pl.tap_step, o[1]);
@@ -481,15 +489,13 @@ lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
     put(v, pl.ta, o[6]);
     put(v, pl.opt_strike, o[7]);
     put(v, pl.weight, o[8]);
-    lv_status st = ensure(ctx, ctx->planbuf, v.size());
-    if (st != LV_OK) return st;
-    if (v != ctx->plan_bytes) {
-        // the stream may still read the old tables
-        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
-        HIPCHECK(ctx, hipMemcpy(ctx->planbuf.p, v.data(), v.size(), hipMemcpyHostToDevice));
-        ctx->plan_bytes.swap(v);
-    }
-    char *b = (char *)ctx->planbuf.p;
+    return v;
+}
+
+Tables tables_at(const void *base, const TableOffsets &to) {
+    const char *b = (const char *)base;
+    const size_t *o = to.o;
+    Tables t;
     t.tj = (const int *)(b + o[0]);
     t.cell_lo = (const int *)(b + o[9]);
     t.tap_step = (const int *)(b + o[1]);
@@ -500,10 +506,40 @@ lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
     t.ta = (const double *)(b + o[6]);
     t.opt_strike = (const double *)(b + o[7]);
     t.weight = (const double *)(b + o[8]);
+    return t;
+}
+
+lv_status upload_tables(lv_ctx *ctx, const Plan &pl, Tables &t) {
+    TableOffsets to;
+    std::vector<char> v = pack_tables(pl, to);
+    lv_status st = ensure(ctx, ctx->planbuf, v.size());
+    if (st != LV_OK) return st;
+    if (v != ctx->plan_bytes) {
+        // the stream may still read the old tables
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
+        HIPCHECK(ctx, hipMemcpy(ctx->planbuf.p, v.data(), v.size(), hipMemcpyHostToDevice));
+        ctx->plan_bytes.swap(v);
+    }
+    t = tables_at(ctx->planbuf.p, to);
     return LV_OK;
 }
 
-lvk::Args make_args(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *sigma_dev) {
+// Device buffers one launch sequence works in: the context's own (grown on demand)
+// or, for the allocation-free entry point, regions of the per-GPU workspace.
+struct Space {
+    void *part = nullptr, *states = nullptr, *ckpt = nullptr, *gtab = nullptr;
+};
+
+Space ctx_space(const lv_ctx *ctx) {
+    Space w;
+    w.part = ctx->part.p;
+    w.states = ctx->states.p;
+    w.ckpt = ctx->ckpt.p;
+    w.gtab = ctx->gtab.p;
+    return w;
+}
+
+lvk::Args make_args(const Space &w, const Plan &pl, const Tables &t, const double *sigma_dev) {
     lvk::Args a{};
     a.I = pl.I;
     a.J = pl.J;
@@ -518,7 +554,7 @@ lvk::Args make_args(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *
     a.tj = t.tj;
     a.ta = t.ta;
     a.cell_lo = t.cell_lo;
-    a.gtab = ctx->gtab.p;
+    a.gtab = w.gtab;
     a.P = pl.P;
     a.key0 = (unsigned)(pl.seed & 0xFFFFFFFFu);
     a.key1 = (unsigned)(pl.seed >> 32);
@@ -609,14 +645,14 @@ lv_status collect_times(lv_ctx *ctx) {
 }
 
 // Launch the whole path for one surface (no allocation, no sync): capturable.
-hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const double *sigma_dev,
-                           bool adjoint, double *price, double *stderr_, double *grad,
-                           double *delta, bool capturing) {
+hipError_t enqueue_surface(lv_ctx *ctx, const Space &w, const Plan &pl, const Tables &t,
+                           const double *sigma_dev, bool adjoint, double *price, double *stderr_,
+                           double *grad, double *delta, bool capturing) {
     hipStream_t st = ctx->stream();
-    lvk::Args a = make_args(ctx, pl, t, sigma_dev);
-    a.part = (double *)ctx->part.p;
-    a.states = ctx->states.p;
-    a.ckpt = ctx->ckpt.p;
+    lvk::Args a = make_args(w, pl, t, sigma_dev);
+    a.part = (double *)w.part;
+    a.states = w.states;
+    a.ckpt = w.ckpt;
     const int prof = capturing ? 0 : pl.profile;
     hipError_t e = timed(ctx, prof, LV_K_TABLE, [&](lvk::Ev ev) { return lvk::launch_table(a, pl.precision, st, ev); });
     if (e != hipSuccess) return e;
@@ -648,7 +684,8 @@ hipError_t enqueue_surface(lv_ctx *ctx, const Plan &pl, const Tables &t, const d
     return e;
 }
 
-void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed) {
+void record_info(lv_ctx *ctx, const Plan &pl, bool adjoint, bool replayed, const void *part) {
+    ctx->last_part = part;
     ctx->last_Q = pl.Q;
     ctx->last_G = pl.G;
     ctx->last_nopt = pl.n_opt;
@@ -794,7 +831,7 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
     if ((s = ensure_workspace(ctx, pl, adjoint)) != LV_OK) return s;
     auto enqueue_all = [&]() -> hipError_t {
         for (int k = 0; k < n_surf; ++k) {
-            hipError_t e = enqueue_surface(ctx, pl, t, sigmas_dev + (size_t)k * pl.G, adjoint,
+            hipError_t e = enqueue_surface(ctx, ctx_space(ctx), pl, t, sigmas_dev + (size_t)k * pl.G, adjoint,
                                            prices + (size_t)k * pl.n_opt, stderrs + (size_t)k * pl.n_opt,
                                            grads ? grads + (size_t)k * pl.G : nullptr,
                                            deltas ? deltas + k : nullptr, use_graph);
@@ -805,7 +842,7 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
     if (!use_graph) {
         hipError_t e = enqueue_all();
         if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
-        record_info(ctx, pl, adjoint, false);
+        record_info(ctx, pl, adjoint, false, ctx->part.p);
         return LV_OK;
     }
     const void *ptrs[] = {sigmas_dev, prices, stderrs, grads, deltas, ctx->planbuf.p, ctx->part.p,
@@ -835,7 +872,7 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
         ctx->graph_key = key;
     }
     HIPCHECK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream()));
-    record_info(ctx, pl, adjoint, replay);
+    record_info(ctx, pl, adjoint, replay, ctx->part.p);
     return LV_OK;
 }
 
@@ -870,6 +907,13 @@ lv_status lv_create(lv_ctx **out, int device, void *hip_stream) {
     if (e != hipSuccess) {
         delete c;
         return fail(nullptr, LV_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    // the allocation-free entry point's workspace on this device (looked up once per device)
+    e = lvk::scratch_address(device, &c->scratch);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(c->own_stream);
+        delete c;
+        return fail(nullptr, LV_ERR_HIP, "workspace address on device %d: %s", device, hipGetErrorString(e));
     }
     *out = c;
     return LV_OK;
@@ -927,6 +971,74 @@ lv_status lv_price_and_grad_dev(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf
     HIPCHECK(ctx, hipSetDevice(ctx->device));
     return run_dev(ctx, pl, n_surf, sigmas_dev, adjoint, opts && opts->use_graph, prices_dev,
                    std_errs_dev, grads_dev, deltas_dev);
+}
+
+lv_status lv_price_and_grad_noalloc(lv_ctx *ctx, const lv_grid *grid, int32_t n_surf,
+                                    const double *sigmas_dev, double spot, const lv_book *book,
+                                    int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                    const lv_opts *opts, double *prices_dev, double *std_errs_dev,
+                                    double *grads_dev, double *deltas_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigmas_dev || !prices_dev || !std_errs_dev) return fail(ctx, LV_ERR_ARG, "sigmas, prices and std_errs are required");
+    if (opts && (opts->use_graph || opts->autotune || opts->profile))
+        return fail(ctx, LV_ERR_ARG, "the allocation-free entry point takes no use_graph, autotune or profile");
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, n_surf, nullptr, spot, book, n_paths, n_steps, seed, opts,
+                               ctx->n_cu, ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    const bool adjoint = grads_dev || deltas_dev;
+    if (adjoint && pl.adjoint == LV_ADJ_NONE)
+        return fail(ctx, LV_ERR_ARG, "gradient or delta requested with adjoint mode NONE");
+    // a launch shape this context has tuned for the request is taken as it is
+    auto it = ctx->tuned.find(tune_key(pl, adjoint));
+    if (it != ctx->tuned.end() && (s = apply_shape(ctx, pl, it->second, ctx->n_cu, ctx->max_lds, false, false)) != LV_OK)
+        return s;
+    if (!ctx->scratch) return fail(ctx, LV_ERR_HIP, "no workspace on device %d", ctx->device);
+    // carve the workspace: tables, vol table, block records, then states or checkpoints
+    TableOffsets to;
+    std::vector<char> tab = pack_tables(pl, to);
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = used;
+        used = (used + bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t rb = real_bytes(pl.precision);
+    const size_t o_tab = take(tab.size());
+    const size_t o_gtab = take((size_t)pl.N * pl.I * 2 * rb);
+    const size_t o_part = take((size_t)std::max(pl.blocks, pl.fblocks) * pl.Q * 8);
+    size_t o_states = 0, o_ckpt = 0;
+    if (adjoint && pl.adjoint == LV_ADJ_STORED) o_states = take((size_t)pl.N * (size_t)pl.P * rb);
+    if (adjoint && pl.adjoint == LV_ADJ_CHECKPOINT)
+        o_ckpt = take((size_t)((pl.N + pl.seg - 1) / pl.seg) * pl.CH * pl.blocks * pl.block * rb);
+    if (used > lvk::kScratchBytes)
+        return fail(ctx, LV_ERR_UNSUPPORTED,
+                    "request needs %zu bytes of workspace; the allocation-free entry point has %zu "
+                    "(fewer paths, the checkpointed adjoint or the allocating entry point fit it)",
+                    used, lvk::kScratchBytes);
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    char *base = (char *)ctx->scratch;
+    hipStream_t st = ctx->stream();
+    // the host copy stays with the context until the next such call
+    ctx->scratch_tables.swap(tab);
+    HIPCHECK(ctx, hipMemcpyAsync(base + o_tab, ctx->scratch_tables.data(), ctx->scratch_tables.size(),
+                                 hipMemcpyHostToDevice, st));
+    const Tables t = tables_at(base + o_tab, to);
+    Space w;
+    w.gtab = base + o_gtab;
+    w.part = base + o_part;
+    w.states = o_states ? base + o_states : nullptr;
+    w.ckpt = o_ckpt ? base + o_ckpt : nullptr;
+    for (int k = 0; k < n_surf; ++k) {
+        hipError_t e = enqueue_surface(ctx, w, pl, t, sigmas_dev + (size_t)k * pl.G, adjoint,
+                                       prices_dev + (size_t)k * pl.n_opt, std_errs_dev + (size_t)k * pl.n_opt,
+                                       grads_dev ? grads_dev + (size_t)k * pl.G : nullptr,
+                                       deltas_dev ? deltas_dev + k : nullptr, true);
+        if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    ctx->last_autotuned = false;
+    record_info(ctx, pl, adjoint, false, w.part);
+    return LV_OK;
 }
 
 lv_status lv_bump_grad_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
@@ -1033,7 +1145,7 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
     if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
     if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
     hipStream_t st = ctx->stream();
-    lvk::Args a = make_args(ctx, pl, t, sigma_dev);
+    lvk::Args a = make_args(ctx_space(ctx), pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
     a.states = states_dev;
     a.n_tiles = pl.f_n_tiles;
@@ -1043,7 +1155,7 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
         e = lvk::launch_merge(a.part, pl.fblocks, pl.blocks, pl.Q, pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot,
                               price_dev, std_err_dev, nullptr, nullptr, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
-    record_info(ctx, pl, false, false);
+    record_info(ctx, pl, false, false, ctx->part.p);
     return LV_OK;
 }
 
@@ -1067,7 +1179,7 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     if ((s = ensure_workspace(ctx, pl, false)) != LV_OK) return s;
     if ((s = ensure(ctx, ctx->out_stage, (size_t)2 * pl.n_opt * 8)) != LV_OK) return s;
     hipStream_t st = ctx->stream();
-    lvk::Args a = make_args(ctx, pl, t, sigma_dev);
+    lvk::Args a = make_args(ctx_space(ctx), pl, t, sigma_dev);
     a.part = (double *)ctx->part.p;
     a.states = const_cast<void *>(states_dev);
     a.cot = cotangent_dev;
@@ -1079,7 +1191,7 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
         e = lvk::launch_merge(a.part, pl.blocks, pl.blocks, pl.Q, pl.n_opt, pl.G, t.opt_orig, pl.P, pl.spot,
                               scratch, scratch + pl.n_opt, grad_dev, delta_dev, st);
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
-    record_info(ctx, pl, true, false);
+    record_info(ctx, pl, true, false, ctx->part.p);
     ctx->info.fixed_point_bits = -1000;   // depends on the device cotangent
     return LV_OK;
 }
@@ -1162,11 +1274,11 @@ lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info) {
 lv_status lv_debug_block_partials(lv_ctx *ctx, double *host_out, size_t host_len) {
     if (!ctx || !host_out) return fail(ctx, LV_ERR_ARG, "ctx and host_out are required");
     const int B = ctx->info.n_blocks, Q = ctx->last_Q;
-    if (B <= 0 || !ctx->part.p) return fail(ctx, LV_ERR_ARG, "no pricing call has run on this context");
+    if (B <= 0 || !ctx->last_part) return fail(ctx, LV_ERR_ARG, "no pricing call has run on this context");
     if (host_len < (size_t)B * Q) return fail(ctx, LV_ERR_ARG, "host_out holds %zu doubles, need %zu", host_len, (size_t)B * Q);
     HIPCHECK(ctx, hipSetDevice(ctx->device));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream()));
-    HIPCHECK(ctx, hipMemcpy(host_out, ctx->part.p, (size_t)B * Q * 8, hipMemcpyDeviceToHost));
+    HIPCHECK(ctx, hipMemcpy(host_out, ctx->last_part, (size_t)B * Q * 8, hipMemcpyDeviceToHost));
     return LV_OK;
 }
 

@@ -86,6 +86,14 @@ hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_
 hipError_t launch_bump(const double *sigma, int G, int m0, int mc, double eps, double *out, hipStream_t st);
 hipError_t launch_fd(const double *prices, int n_opt, const double *weight, int m0, int mc, double eps,
                      double *grad, hipStream_t st);
+// Size of the per-GPU workspace of the allocation-free entry point, and the devices
+// whose address is kept.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+// Address of that workspace on `device`, which must be the current device; read with
+// hipGetSymbolAddress on the first call per device and kept.
+hipError_t scratch_address(int device, void **out);
+
 hipError_t launch_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
                                unsigned long long p0, long long n_paths, uint32_t *out,
                                hipStream_t st);

@@ -30,6 +30,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lv_internal.h"
@@ -1301,6 +1302,35 @@ hipError_t launch_fd(const double *prices, int n_opt, const double *weight, int 
                      double *grad, hipStream_t st) {
     hipLaunchKernelGGL(k_fd, dim3((mc + 255) / 256), dim3(256), 0, st, prices, n_opt, weight, m0, mc, eps, grad);
     return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Workspace of the allocation-free entry point: one array per GPU, held from the
+// module's load until the process ends and shared by every such call on that GPU.
+// Host code never names the array itself (its host-side name is a stand-in, not a
+// device address): the address is read once per device with hipGetSymbolAddress and
+// passed to the kernels like any other buffer.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_debug_philox(unsigned long long seed, unsigned long long m0, int n_m,
