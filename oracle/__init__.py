@@ -83,16 +83,19 @@ class Oracle:
         L.lvo_last_error.restype = C.c_char_p
         L.lvo_accumulate.argtypes = surf + book + [C.c_int32, C.c_uint64, C.c_int64, _lp,
                                                    C.c_int32, _dp, _dp, C.c_void_p, C.c_void_p,
-                                                   C.c_int32]
+                                                   C.c_int32, C.c_double]
         L.lvo_accumulate.restype = C.c_int
         L.lvo_path.argtypes = surf + book + [C.c_int32, C.c_uint64, C.c_int64,
-                                             _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int32]
+                                             _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int32, C.c_double]
         L.lvo_path.restype = C.c_int
         L.lvo_interp_at.argtypes = surf + [C.c_double, C.c_double, C.POINTER(C.c_double),
                                            C.POINTER(C.c_double), _ip, _dp]
         L.lvo_interp_at.restype = C.c_int
         L.lvo_round_bf16.argtypes = [C.c_double]
         L.lvo_round_bf16.restype = C.c_double
+        L.lvo_path_state_bound.argtypes = surf + book + [C.c_int32, C.c_uint64, C.c_int64, _dp, _dp, _ip,
+                                                         C.c_double]
+        L.lvo_path_state_bound.restype = C.c_int
 
     def _check(self, rc):
         if rc != 0:
@@ -135,21 +138,22 @@ class Oracle:
 
     # -- one path ----------------------------------------------------------
     def path(self, surface, book, n_steps: int, seed: int, p: int, spot: float = 100.0,
-             scheme: int = 0) -> Dict:
+             scheme: int = 0, rate: float = 0.0) -> Dict:
         N = int(n_steps)
         G = surface.spot_axis.n * surface.time_axis.n
         y, z = np.zeros(N + 1), np.zeros(N)
         sig, dsdy, lam = np.zeros(N), np.zeros(N), np.zeros(N + 1)
         pay, grad = np.zeros(book.n), np.zeros(G)
         self._check(self.lib.lvo_path(*_surface_args(surface), spot, *_book_args(book), N,
-                                      seed, p, y, z, sig, dsdy, lam, pay, grad, int(scheme)))
+                                      seed, p, y, z, sig, dsdy, lam, pay, grad, int(scheme),
+                                      float(rate)))
         return dict(y=y, z=z, sigma=sig, dsdy=dsdy, lam=lam, payoff=pay,
                     grad=grad.reshape(surface.sigma.shape))
 
     # -- sums over path ranges ---------------------------------------------
     def sums(self, surface, book, n_steps: int, seed: int,
              ranges: Sequence[Tuple[int, int]], n_threads: int = 0, spot: float = 100.0,
-             want_grad: bool = True, scheme: int = 0) -> Dict:
+             want_grad: bool = True, scheme: int = 0, rate: float = 0.0) -> Dict:
         """Unnormalised sums of payoff, payoff^2, grid gradient and d/dy_0 of the
         weighted book value over the given half-open path ranges."""
         if n_threads <= 0:
@@ -162,7 +166,7 @@ class Oracle:
         self._check(self.lib.lvo_accumulate(
             *_surface_args(surface), spot, *_book_args(book), int(n_steps), seed,
             rg.shape[0], rg, n_threads, s1, s2,
-            grad.ctypes.data if want_grad else None, lam0.ctypes.data, int(scheme)))
+            grad.ctypes.data if want_grad else None, lam0.ctypes.data, int(scheme), float(rate)))
         n = int(np.sum(rg[:, 1] - rg[:, 0]))
         return dict(n=n, sum_pay=s1, sum_pay2=s2,
                     sum_grad=grad.reshape(surface.sigma.shape) if want_grad else None,
@@ -170,12 +174,12 @@ class Oracle:
 
     def price_and_grad(self, surface, book, n_paths: int, n_steps: int, seed: int = 0,
                        n_threads: int = 0, spot: float = 100.0, want_grad: bool = True,
-                       path0: int = 0, scheme: int = 0) -> Dict:
+                       path0: int = 0, scheme: int = 0, rate: float = 0.0) -> Dict:
         """Price, standard error per option, gradient of the weighted book value
         with respect to every vol node, and delta (d value / d spot).  scheme 0:
         log-Euler on ln X; 1: the Euler step on X itself."""
         s = self.sums(surface, book, n_steps, seed, [(path0, path0 + n_paths)], n_threads,
-                      spot, want_grad, scheme)
+                      spot, want_grad, scheme, rate)
         P = float(n_paths)
         price = s["sum_pay"] / P
         var = (s["sum_pay2"] - s["sum_pay"] ** 2 / P) / (P - 1.0)
@@ -186,7 +190,7 @@ class Oracle:
 
     def bump_grad(self, surface, book, n_paths: int, n_steps: int, seed: int = 0, eps: float = 1e-4,
                   nodes: Optional[Sequence[Tuple[int, int]]] = None, n_threads: int = 0,
-                  spot: float = 100.0, scheme: int = 0) -> np.ndarray:
+                  spot: float = 100.0, scheme: int = 0, rate: float = 0.0) -> np.ndarray:
         """Finite-difference ("bumping", Sec. III) derivative of the weighted book value
         with respect to the listed nodes (all when None): the book priced on the same
         paths with sigma_ij + eps/2 and with sigma_ij - eps/2, the difference over eps.
@@ -203,11 +207,31 @@ class Oracle:
                 sig[i, j] += h
                 bumped = dataclasses.replace(surface, sigma=sig)
                 r = self.price_and_grad(bumped, book, n_paths, n_steps, seed, n_threads, spot,
-                                        want_grad=False, scheme=scheme)
+                                        want_grad=False, scheme=scheme, rate=rate)
                 vals.append(float(np.dot(w, r["price"])))
             out[q] = (vals[0] - vals[1]) / eps
         return out
 
+
+    # -- how far a single-precision computation of a path can be -----------
+    def path_state_bound(self, surface, book, n_steps: int, seed: int, p: int, spot: float = 100.0,
+                         model=None, rate: float = 0.0):
+        """First-order bound e[N+1] on |y_n(single precision) - y_n(this oracle)| for path p
+        of the log-Euler scheme, and the steps [N] whose spot cell is undecided at that
+        precision (lvo_path_state_bound in lv_oracle.c)."""
+        model = np.ascontiguousarray(FP32_MODEL if model is None else model, dtype=np.float64)
+        N = int(n_steps)
+        e, und = np.zeros(N + 1), np.zeros(N, dtype=np.int32)
+        self._check(self.lib.lvo_path_state_bound(*_surface_args(surface), spot, *_book_args(book), N,
+                                                  seed, p, model, e, und, float(rate)))
+        return e, und.astype(bool)
+
+
+# Unit roundoff of IEEE single precision; the local error of one step's increment and
+# of the cell coordinate, in units of it (hardware log/sqrt/sin/cos and exp of a few
+# ulps each, a handful of rounded products and sums); the safety margin on the
+# coordinate.
+FP32_MODEL = (2.0 ** -24, 8.0, 8.0, 4.0)
 
 _default: Optional[Oracle] = None
 

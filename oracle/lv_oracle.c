@@ -10,10 +10,13 @@
  * share no source.
  *
  * What it computes, in the paper's terms:
- *   - the model dX/X = sigma(X,t) dW, no drift (Sec. IV-A, the SDE);
+ *   - the model dX/X = sigma(X,t) dW (Sec. IV-A, the SDE), or with a constant
+ *     short rate r the trend r dt that the narrated step adds ("today's price
+ *     plus a deterministic trend plus a Gaussian term"), payoffs then discounted
+ *     by e^{-r T}; r = 0 is the paper's driftless SDE;
  *   - an explicit Euler scheme (Sec. IV-A), taken on y = ln(X/X0) with the Ito
- *     drift -sigma^2/2, sigma read at the left point of each step; or (scheme 1)
- *     the explicit Euler step on X itself, as the paper narrates the scheme;
+ *     drift (r - sigma^2/2) dt, sigma read at the left point of each step; or
+ *     (scheme 1) the explicit Euler step on X itself, as the paper narrates it;
  *   - sigma(S,t) by bilinear interpolation of a grid of nodes {(i dx, j dt)}
  *     (Sec. IV-A, the grid; Sec. IV-D, bilinear interpolation), flat outside;
  *   - Gaussian increments from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
@@ -124,9 +127,11 @@ typedef struct {
     int32_t n_steps;
     uint64_t seed;
     int32_t scheme;              /* 0: log-Euler on y = ln(X/X0); 1: Euler on X */
+    double rate;                 /* constant short rate r: the step's trend, e^{-r T} discounting */
     /* derived */
     double dt, sqrt_dt;
     int32_t *tap_step;           /* [n_opt] step index of each maturity */
+    double *disc;                /* [n_opt] discount factor e^{-r T_k} */
 } lvo_problem;
 
 static char lvo_errbuf[256];
@@ -147,6 +152,7 @@ static int lvo_setup(lvo_problem *pb)
     if (!(pb->spot > 0.0)) return lvo_fail("spot must be positive");
     if (pb->n_opt < 1 || pb->n_steps < 1) return lvo_fail("need n_opt >= 1 and n_steps >= 1");
     if (pb->scheme != 0 && pb->scheme != 1) return lvo_fail("unknown scheme");
+    if (!isfinite(pb->rate)) return lvo_fail("rate must be finite");
     for (int64_t q = 0; q < (int64_t)pb->n_spot * pb->n_time; ++q)
         if (!(isfinite(pb->sigma[q]) && pb->sigma[q] > 0.0)) return lvo_fail("sigma nodes must be finite and positive");
     double tmax = 0.0;
@@ -167,7 +173,17 @@ static int lvo_setup(lvo_problem *pb)
         }
         pb->tap_step[k] = (int32_t)r;
     }
+    pb->disc = (double *)malloc(sizeof(double) * pb->n_opt);
+    for (int k = 0; k < pb->n_opt; ++k) pb->disc[k] = exp(-pb->rate * pb->maturity[k]);
     return 0;
+}
+
+static void lvo_release(lvo_problem *pb)
+{
+    free(pb->tap_step);
+    free(pb->disc);
+    pb->tap_step = NULL;
+    pb->disc = NULL;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -287,10 +303,10 @@ static void lvo_one_path(const lvo_problem *pb, uint64_t p, lvo_work *w,
         lvo_eval(pb, S, n * dt, &w->iv[n]);
         w->z[n] = lvo_normal(pb->seed, p, n);
         double s = w->iv[n].sigma;
-        w->y[n + 1] = w->y[n] - 0.5 * s * s * dt + s * sdt * w->z[n];
+        w->y[n + 1] = w->y[n] + (pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n];
     }
     for (int k = 0; k < pb->n_opt; ++k)
-        payoffs[k] = lvo_payoff(pb, k, w->y[pb->tap_step[k]]);
+        payoffs[k] = pb->disc[k] * lvo_payoff(pb, k, w->y[pb->tap_step[k]]);
 
     double lam = 0.0;
     int32_t J = pb->n_time;
@@ -298,7 +314,7 @@ static void lvo_one_path(const lvo_problem *pb, uint64_t p, lvo_work *w,
         for (int k = 0; k < pb->n_opt; ++k)
             if (pb->tap_step[k] == n) {
                 double wk = pb->weight ? pb->weight[k] : 1.0;
-                lam += wk * lvo_dpayoff_dy(pb, k, w->y[n]);
+                lam += wk * pb->disc[k] * lvo_dpayoff_dy(pb, k, w->y[n]);
             }
         if (lam_hist) lam_hist[n] = lam;
         const lvo_interp *iv = &w->iv[n - 1];
@@ -335,18 +351,18 @@ static void lvo_one_path_euler_x(const lvo_problem *pb, uint64_t p, lvo_work *w,
     for (int32_t n = 0; n < N; ++n) {
         lvo_eval(pb, X[n], n * dt, &w->iv[n]);
         w->z[n] = lvo_normal(pb->seed, p, n);
-        X[n + 1] = X[n] + w->iv[n].sigma * X[n] * sdt * w->z[n];
+        X[n + 1] = X[n] + pb->rate * X[n] * dt + w->iv[n].sigma * X[n] * sdt * w->z[n];
     }
     for (int k = 0; k < pb->n_opt; ++k) {
         double x = X[pb->tap_step[k]], K = pb->strike[k];
-        payoffs[k] = pb->is_put[k] ? (K > x ? K - x : 0.0) : (x > K ? x - K : 0.0);
+        payoffs[k] = pb->disc[k] * (pb->is_put[k] ? (K > x ? K - x : 0.0) : (x > K ? x - K : 0.0));
     }
     double lam = 0.0;
     int32_t J = pb->n_time;
     for (int32_t n = N; n >= 1; --n) {
         for (int k = 0; k < pb->n_opt; ++k)
             if (pb->tap_step[k] == n) {
-                double wk = pb->weight ? pb->weight[k] : 1.0, K = pb->strike[k];
+                double wk = (pb->weight ? pb->weight[k] : 1.0) * pb->disc[k], K = pb->strike[k];
                 if (pb->is_put[k]) lam -= K > X[n] ? wk : 0.0;
                 else lam += X[n] > K ? wk : 0.0;
             }
@@ -362,7 +378,7 @@ static void lvo_one_path_euler_x(const lvo_problem *pb, uint64_t p, lvo_work *w,
             grad[q00 + J + 1] += lam * c * iv->w[3];
         }
         /* X d sigma / d X = d sigma / d ln X */
-        lam = lam * (1.0 + sdt * w->z[n - 1] * (iv->sigma + iv->dsigma_dy));
+        lam = lam * (1.0 + pb->rate * dt + sdt * w->z[n - 1] * (iv->sigma + iv->dsigma_dy));
     }
     if (lam_hist) lam_hist[0] = lam * X[0];
     *lam0 = lam * X[0];
@@ -445,16 +461,16 @@ int lvo_accumulate(int32_t n_spot, int32_t spot_kind, double spot_lo, double spo
                    const double *maturity, const double *weight, int32_t n_steps, uint64_t seed,
                    int64_t n_ranges, const int64_t *ranges, int32_t n_threads,
                    double *sum_pay, double *sum_pay2, double *sum_grad, double *sum_lam0,
-                   int32_t scheme)
+                   int32_t scheme, double rate)
 {
     lvo_problem pb = {n_spot, spot_kind, spot_lo, spot_hi, n_time, time_lo, time_hi, sigma,
-                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, scheme, 0, 0, NULL};
+                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, scheme, rate, 0, 0, NULL, NULL};
     if (lvo_setup(&pb) != 0) return -1;
 
     int64_t n_chunks = 0;
     for (int64_t r = 0; r < n_ranges; ++r) {
         int64_t len = ranges[2 * r + 1] - ranges[2 * r];
-        if (len < 0 || ranges[2 * r] < 0) { free(pb.tap_step); return lvo_fail("bad path range"); }
+        if (len < 0 || ranges[2 * r] < 0) { lvo_release(&pb); return lvo_fail("bad path range"); }
         n_chunks += (len + LVO_CHUNK - 1) / LVO_CHUNK;
     }
     lvo_chunk *chunks = (lvo_chunk *)malloc(sizeof(lvo_chunk) * (n_chunks > 0 ? n_chunks : 1));
@@ -501,7 +517,7 @@ int lvo_accumulate(int32_t n_spot, int32_t spot_kind, double spot_lo, double spo
     free(sum); free(comp);
     free(job.chunk_out);
     free(chunks);
-    free(pb.tap_step);
+    lvo_release(&pb);
     return 0;
 }
 
@@ -516,10 +532,10 @@ int lvo_path(int32_t n_spot, int32_t spot_kind, double spot_lo, double spot_hi,
              double spot, int32_t n_opt, const int32_t *is_put, const double *strike,
              const double *maturity, const double *weight, int32_t n_steps, uint64_t seed,
              int64_t p, double *y, double *z, double *sig, double *dsdy, double *lam,
-             double *payoff, double *grad, int32_t scheme)
+             double *payoff, double *grad, int32_t scheme, double rate)
 {
     lvo_problem pb = {n_spot, spot_kind, spot_lo, spot_hi, n_time, time_lo, time_hi, sigma,
-                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, scheme, 0, 0, NULL};
+                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, scheme, rate, 0, 0, NULL, NULL};
     if (lvo_setup(&pb) != 0) return -1;
     lvo_work w;
     lvo_work_alloc(&w, n_steps);
@@ -535,7 +551,7 @@ int lvo_path(int32_t n_spot, int32_t spot_kind, double spot_lo, double spot_hi,
         dsdy[n] = w.iv[n].dsigma_dy;
     }
     lvo_work_free(&w);
-    free(pb.tap_step);
+    lvo_release(&pb);
     return 0;
 }
 
@@ -595,4 +611,82 @@ double lvo_round_bf16(double v)
     else if (d_hi < d_lo) pick = above;
     else pick = (below & 0x10000u) ? above : below;
     return (double)lvo_bits_to_float(sign | pick);
+}
+
+/* ------------------------------------------------------------------------- */
+/* How far a single-precision computation of a path can be from this one.     */
+/*                                                                           */
+/* TEST SUPPORT, like the rest of this file.  A computation of the same       */
+/* log-Euler path (Sec. IV-A) in IEEE single precision makes a local error in */
+/* every step, and the step map carries earlier errors forward with its       */
+/* derivative J_n = d y_{n+1} / d y_n = 1 + c_n s'_n (c_n = d y_{n+1} /       */
+/* d sigma_n, s'_n = d sigma / d y at the step: the factors of the adjoint    */
+/* recursion).  To first order the state error is bounded by the running sum  */
+/*   e_0 = 0,   e_{n+1} = |J_n| e_n + rho_n,                                 */
+/*   rho_n = u (k_step (|sigma_n sqrt(dt) Z_n| + sigma_n^2 dt / 2) + |y_{n+1}|) */
+/* -- the increment computed with relative error k_step u, the new state      */
+/* rounded -- with u the unit roundoff.  The grid coordinate a_n is then      */
+/* known to within da_n = M (|da/dy| e_n + k_coord u (|a_n| + S_n / du on a    */
+/* linear axis)), M a safety margin; where the nearest spot node lies within  */
+/* da_n of a_n the step's cell is undecided at that precision (the slope of   */
+/* the bilinear surface jumps there) and |J_n| takes its largest value over   */
+/* the cells at the node.  model = {u, k_step, k_coord, M}; e[N+1];           */
+/* undecided[N].                                                              */
+/* ------------------------------------------------------------------------- */
+static double lvo_cell_slope_dy(const lvo_problem *pb, int c, double t, double S, double du)
+{
+    if (c < 0 || c > pb->n_spot - 2) return 0.0;
+    int32_t j;
+    double alpha;
+    lvo_time_cell_at(pb, t, &j, &alpha);
+    const double *sg = pb->sigma;
+    int32_t J = pb->n_time;
+    double dsdu = ((1.0 - alpha) * (sg[(c + 1) * J + j] - sg[c * J + j]) +
+                   alpha * (sg[(c + 1) * J + j + 1] - sg[c * J + j + 1])) / du;
+    return pb->spot_kind == 0 ? dsdu * S : dsdu;
+}
+
+int lvo_path_state_bound(int32_t n_spot, int32_t spot_kind, double spot_lo, double spot_hi,
+                         int32_t n_time, double time_lo, double time_hi, const double *sigma,
+                         double spot, int32_t n_opt, const int32_t *is_put, const double *strike,
+                         const double *maturity, const double *weight, int32_t n_steps, uint64_t seed,
+                         int64_t p, const double *model, double *e, int32_t *undecided, double rate)
+{
+    lvo_problem pb = {n_spot, spot_kind, spot_lo, spot_hi, n_time, time_lo, time_hi, sigma,
+                      spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, 0, rate, 0, 0, NULL, NULL};
+    if (lvo_setup(&pb) != 0) return -1;
+    const double u = model[0], ks = model[1], kc = model[2], M = model[3];
+    lvo_work w;
+    lvo_work_alloc(&w, n_steps);
+    double *pay = (double *)malloc(sizeof(double) * n_opt);
+    double lam0;
+    lvo_one_path(&pb, (uint64_t)p, &w, pay, NULL, &lam0, NULL);
+    const double u0 = spot_kind == 0 ? spot_lo : log(spot_lo);
+    const double u1 = spot_kind == 0 ? spot_hi : log(spot_hi);
+    const double du = (u1 - u0) / (n_spot - 1), dt = pb.dt, sdt = pb.sqrt_dt;
+    e[0] = 0.0;
+    for (int32_t n = 0; n < n_steps; ++n) {
+        const lvo_interp *iv = &w.iv[n];
+        const double S = spot * exp(w.y[n]);
+        const double a = ((spot_kind == 0 ? S : log(S)) - u0) / du;
+        const double da = M * ((spot_kind == 0 ? S / du : 1.0 / du) * e[n] +
+                               kc * u * (fabs(a) + (spot_kind == 0 ? S / du : 0.0)));
+        const double c = -iv->sigma * dt + sdt * w.z[n];
+        double jn = fabs(1.0 + c * iv->dsigma_dy);
+        double k = floor(a + 0.5);
+        if (k < 0.0) k = 0.0;
+        if (k > n_spot - 1) k = n_spot - 1;
+        undecided[n] = fabs(a - k) <= da;
+        if (undecided[n]) {
+            const int32_t kn = (int32_t)k;
+            jn = fmax(jn, fabs(1.0 + c * lvo_cell_slope_dy(&pb, kn - 1, n * dt, S, du)));
+            jn = fmax(jn, fabs(1.0 + c * lvo_cell_slope_dy(&pb, kn, n * dt, S, du)));
+        }
+        e[n + 1] = jn * e[n] + u * (ks * (fabs(iv->sigma * sdt * w.z[n]) + 0.5 * iv->sigma * iv->sigma * dt) +
+                                    fabs(w.y[n + 1]));
+    }
+    free(pay);
+    lvo_work_free(&w);
+    lvo_release(&pb);
+    return 0;
 }

@@ -158,3 +158,35 @@ def fd_on(fn, surface, eps: float = 1e-6):
             g[i, j] = (fn(Surface(surface.spot_axis, surface.time_axis, up))
                        - fn(Surface(surface.spot_axis, surface.time_axis, dn))) / eps
     return g
+
+
+# --------------------------------------------------------------------------
+# with a constant short rate r (discounted prices)
+# --------------------------------------------------------------------------
+def bs_call_r(S, K, sigma, T, r):
+    """Black-Scholes call with rate r: S N(d1) - K e^{-rT} N(d2)."""
+    v = sigma * math.sqrt(T)
+    d1 = (math.log(S / K) + (r + 0.5 * sigma * sigma) * T) / v
+    return S * float(ndtr(d1)) - K * math.exp(-r * T) * float(ndtr(d1 - v))
+
+
+def bs_put_r(S, K, sigma, T, r):
+    """Put by parity: call - S + K e^{-rT}."""
+    return bs_call_r(S, K, sigma, T, r) - S + K * math.exp(-r * T)
+
+
+def bs_vega_r(S, K, sigma, T, r):
+    """d call / d sigma with rate r: S phi(d1) sqrt(T)."""
+    v = sigma * math.sqrt(T)
+    d1 = (math.log(S / K) + (r + 0.5 * sigma * sigma) * T) / v
+    return S * float(npdf(d1)) * math.sqrt(T)
+
+
+def euler_x_call_1step_r(S, K, a, rT):
+    """Call on X_1 = S (1 + rT + a Z) (one Euler step on X with trend rT and
+    a = sigma sqrt(T)), undiscounted: X_1 is Gaussian with mean m = S (1 + rT) and sd
+    S a, so the expectation is (m - K) Phi(d) + S a phi(d), d = (m - K) / (S a); its
+    derivative in a is S phi(d)."""
+    m = S * (1.0 + rT)
+    d = (m - K) / (S * a)
+    return (m - K) * ndtr(d) + S * a * float(npdf(d)), S * float(npdf(d))

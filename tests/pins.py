@@ -20,6 +20,9 @@ What pins what:
   * zero buckets          -- nodes no path can reach are exactly zero
   * bfloat16 nodes        -- torch's float32 -> bfloat16 conversion (a library routine),
                              exact ties between neighbours, the two-step rounding
+  * a constant rate       -- Black-Scholes with the rate and its vega, discounted
+                             put-call parity and martingale, one step of either scheme,
+                             bumping with common random numbers
 """
 from __future__ import annotations
 
@@ -37,13 +40,13 @@ from tests import closed_forms as cf
 SQRT_TAIL = math.sqrt(-2.0 * math.log(2.0 ** -24))   # largest |Z| the 23-bit uniform allows
 
 
-def _batch_stats(o, surface, book, n_steps, n_paths, n_batches, seed=0, spot=100.0, scheme=0):
+def _batch_stats(o, surface, book, n_steps, n_paths, n_batches, seed=0, spot=100.0, scheme=0, rate=0.0):
     """Price and gradient by batch means: mean over batches and the standard error
     of that mean, for the weighted book value."""
     per = n_paths // n_batches
     vals, grads = [], []
     for b in range(n_batches):
-        s = o.sums(surface, book, n_steps, seed, [(b * per, (b + 1) * per)], spot=spot, scheme=scheme)
+        s = o.sums(surface, book, n_steps, seed, [(b * per, (b + 1) * per)], spot=spot, scheme=scheme, rate=rate)
         vals.append(float(np.dot(book.weight, s["sum_pay"])) / per)
         grads.append(s["sum_grad"] / per)
     vals, grads = np.array(vals), np.array(grads)
@@ -474,3 +477,116 @@ def pin_round_bf16(o):
     assert np.array_equal(o.round_bf16(b), b)
     ulp32 = np.spacing(mid32).astype(np.float64)
     assert np.array_equal(o.round_bf16(mid + 0.25 * ulp32), even)
+
+
+# --------------------------------------------------------------------------
+# a constant short rate: the trend of the narrated step (Sec. IV-A), payoffs
+# discounted by e^{-r T}
+# --------------------------------------------------------------------------
+RATE = 0.05
+
+
+def pin_rate_black_scholes(o, n_paths=1 << 17, n_batches=32):
+    """Flat vol with r = 0.05: log-Euler stays exact in law, so the discounted calls and
+    put are Black-Scholes with the rate (within 4 standard errors); per path, the grid
+    gradient sums to the discounted pathwise vega e^{-rT} S_T 1{S_T>K} (-sigma T +
+    sqrt(dt) sum Z) with y_N = (r - sigma^2/2) T + sigma sqrt(dt) sum Z; by batch means
+    the sum of the grid gradient is the Black-Scholes vega S0 phi(d1) sqrt(T)."""
+    s = W.flat_surface(W.small_surface(), 0.2)
+    book = W.Book([0, 1, 0], [100.0, 110.0, 80.0], [1.0, 1.0, 0.5], [1.0, 1.0, 1.0])
+    r = o.price_and_grad(s, book, n_paths, 52, seed=5, rate=RATE)
+    ref = [cf.bs_call_r(100, 100, 0.2, 1.0, RATE), cf.bs_put_r(100, 110, 0.2, 1.0, RATE),
+           cf.bs_call_r(100, 80, 0.2, 0.5, RATE)]
+    for k in range(3):
+        assert abs(r["price"][k] - ref[k]) < 4.0 * r["stderr"][k], (k, r["price"][k], ref[k])
+    dt, call = 1.0 / 52, W.call(100.0, 1.0)
+    for p in range(20):
+        q = o.path(s, call, 52, 3, p, rate=RATE)
+        yN = (RATE - 0.02) * 1.0 + 0.2 * math.sqrt(dt) * q["z"].sum()
+        assert abs(q["y"][-1] - yN) < 1e-12
+        ST = 100.0 * math.exp(q["y"][-1])
+        expect = math.exp(-RATE) * (ST if ST > 100.0 else 0.0) * (-0.2 + math.sqrt(dt) * q["z"].sum())
+        assert abs(q["grad"].sum() - expect) <= 1e-11 * max(1.0, abs(expect)), (p, q["grad"].sum(), expect)
+    per = n_paths // n_batches
+    tot = [o.sums(s, call, 52, 8, [(b * per, (b + 1) * per)], rate=RATE)["sum_grad"].sum() / per
+           for b in range(n_batches)]
+    vega = cf.bs_vega_r(100.0, 100.0, 0.2, 1.0, RATE)
+    assert abs(np.mean(tot) - vega) < 4.0 * np.std(tot, ddof=1) / math.sqrt(n_batches), (np.mean(tot), vega)
+
+
+def pin_rate_parity_and_martingale(o, n_paths=1 << 15):
+    """On the smile surface with r = 0.05, for two maturities: call - put =
+    e^{-rT} (mean S_T - K) sample by sample (prices, grids and deltas), and the
+    discounted spot is a martingale of the scheme, E[e^{-rT} S_T] = S0."""
+    s = W.small_surface()
+    K, tiny = 95.0, 1e-9
+    for T in (0.5, 1.0):
+        mat = [T, 1.0]          # the second option fixes dt = 1/52
+        rc = o.price_and_grad(s, W.Book([0, 0], [K, K], mat, [1.0, 0.0]), n_paths, 52, seed=21, rate=RATE)
+        rp = o.price_and_grad(s, W.Book([1, 0], [K, K], mat, [1.0, 0.0]), n_paths, 52, seed=21, rate=RATE)
+        r0 = o.price_and_grad(s, W.Book([0, 0], [tiny, K], mat, [1.0, 0.0]), n_paths, 52, seed=21, rate=RATE)
+        disc = math.exp(-RATE * T)
+        mean_ST = r0["price"][0] + tiny * disc          # = e^{-rT} mean(S_T)
+        assert abs((rc["price"][0] - rp["price"][0]) - (mean_ST - K * disc)) < 1e-11 * 100
+        scale = max(np.abs(r0["grad"]).max(), 1.0)
+        assert np.abs((rc["grad"] - rp["grad"]) - r0["grad"]).max() < 1e-11 * scale
+        assert abs((rc["delta"] - rp["delta"]) - r0["delta"]) < 1e-11
+        assert abs(mean_ST - 100.0) < 4.0 * r0["stderr"][0], (T, mean_ST)
+
+
+def pin_rate_one_step(o, n_paths=1 << 17):
+    """One step with r = 0.05: y_1 = (r - s_0^2/2) T + s_0 sqrt(T) Z, so the call is
+    Black-Scholes with vol s_0 and rate r, and d price / d node = vega(s_0) w_node(S0, 0)."""
+    for kind in (W.LIN, W.LOG):
+        s = W.tiny_surface(kind, 6, 3, seed=9)
+        T, K = 0.25, 103.0
+        r = o.price_and_grad(s, W.call(K, T), n_paths, 1, seed=2, rate=RATE)
+        s0, _, (i, j), w = o.interp(s, 100.0, 0.0)
+        assert abs(r["price"][0] - cf.bs_call_r(100, K, s0, T, RATE)) < 4 * r["stderr"][0]
+        per = n_paths // 32
+        gs = np.array([o.sums(s, W.call(K, T), 1, 2, [(b * per, (b + 1) * per)], rate=RATE)["sum_grad"] / per
+                       for b in range(32)])
+        g, g_se = gs.mean(axis=0), gs.std(axis=0, ddof=1) / math.sqrt(32)
+        dv = cf.bs_vega_r(100, K, s0, T, RATE)
+        expect = np.zeros_like(s.sigma)
+        for (di, dj), wk in zip([(0, 0), (1, 0), (0, 1), (1, 1)], w):
+            expect[i + di, j + dj] += dv * wk
+        mask = expect != 0
+        assert np.all(np.abs(g[mask] - expect[mask]) < 4 * g_se[mask] + 1e-12), (kind, g[mask], expect[mask])
+        assert np.all(r["grad"][~mask] == 0.0)
+
+
+def pin_rate_euler_x_one_step(o, n_paths=1 << 17):
+    """One Euler step on X with r = 0.05: X_1 = S0 (1 + rT + s_0 sqrt(T) Z) is Gaussian,
+    so the discounted call is closed form and d price / d node = e^{-rT} S0 phi(d)
+    sqrt(T) w_node(S0, 0)."""
+    s = W.tiny_surface(W.LIN, 6, 3, seed=9)
+    T, K = 0.25, 103.0
+    r = o.price_and_grad(s, W.call(K, T), n_paths, 1, seed=2, scheme=1, rate=RATE)
+    s0, _, (i, j), w = o.interp(s, 100.0, 0.0)
+    und, d_da = cf.euler_x_call_1step_r(100.0, K, s0 * math.sqrt(T), RATE * T)
+    disc = math.exp(-RATE * T)
+    assert abs(r["price"][0] - disc * und) < 4 * r["stderr"][0]
+    _, _, g, g_se = _batch_stats(o, s, W.call(K, T), 1, n_paths, 32, seed=2, scheme=1, rate=RATE)
+    expect = np.zeros_like(s.sigma)
+    for (di, dj), wk in zip([(0, 0), (1, 0), (0, 1), (1, 1)], w):
+        expect[i + di, j + dj] += disc * d_da * math.sqrt(T) * wk
+    mask = expect != 0
+    assert np.all(np.abs(g[mask] - expect[mask]) < 4 * g_se[mask] + 1e-12)
+
+
+def pin_rate_adjoint_fd(o):
+    """With r = 0.05, the adjoint of both schemes (and the delta) against central
+    bumps on the same streams, for a book of calls and puts of two maturities."""
+    book = W.Book([0, 1, 0], [100.0, 105.0, 92.0], [1.0, 0.5, 0.75], [1.0, 2.5, -0.7])
+    for kind, scheme in ((W.LIN, 0), (W.LOG, 0), (W.LIN, 1), (W.LOG, 1)):
+        s = W.tiny_surface(kind, 5, 4, seed=21 + kind)
+        r = o.price_and_grad(s, book, 512, 8, seed=6, scheme=scheme, rate=RATE)
+        fd = o.bump_grad(s, book, 512, 8, 6, 1e-5, scheme=scheme, rate=RATE).reshape(s.sigma.shape)
+        scale = np.abs(r["grad"]).max()
+        assert np.abs(r["grad"] - fd).max() < 2e-6 * scale, (kind, scheme)
+        h = 1e-4
+        up = o.price_and_grad(s, book, 512, 8, seed=6, spot=100.0 + h, want_grad=False, scheme=scheme, rate=RATE)
+        dn = o.price_and_grad(s, book, 512, 8, seed=6, spot=100.0 - h, want_grad=False, scheme=scheme, rate=RATE)
+        fd_delta = (np.dot(book.weight, up["price"]) - np.dot(book.weight, dn["price"])) / (2 * h)
+        assert abs(r["delta"] - fd_delta) < 1e-6 * max(1.0, abs(fd_delta)), (r["delta"], fd_delta)

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import workloads as W
 
-STATE_UPDATE = "w->y[n + 1] = w->y[n] - 0.5 * s * s * dt + s * sdt * w->z[n];"
+STATE_UPDATE = "w->y[n + 1] = w->y[n] + (pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n];"
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +23,7 @@ def f32_state_oracle(tmp_path_factory):
     src = open(oracle.SOURCE).read()
     assert src.count(STATE_UPDATE) == 1
     path = d / "f32state.c"
-    path.write_text(src.replace(STATE_UPDATE, "w->y[n + 1] = (double)(float)(w->y[n] - 0.5 * s * s * dt + s * sdt * w->z[n]);"))
+    path.write_text(src.replace(STATE_UPDATE, "w->y[n + 1] = (double)(float)(w->y[n] + (pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n]);"))
     return oracle.Oracle(oracle.build(str(path), str(d / "libf32state.so")))
 
 

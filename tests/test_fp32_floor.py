@@ -1,0 +1,146 @@
+"""Why the FP32 gradient is not held to 1e-4 max|g| bucket by bucket on every workload,
+and a pin of the oracle's single-precision state bound (CPU, oracle copies only).
+
+The pathwise derivative of a bilinear surface jumps at spot nodes (Sec. IV-D), and on
+the 5-year noisy 100 x 50 surface the adjoint of some paths -- a product of 260 step
+derivatives -- is very large.  A copy of the oracle whose normals and interpolated vols
+are rounded to float32 exactly (the most accurate single-precision values there are),
+with the state and the cell coordinate kept in double, already moves buckets there by
+far more than 1e-4 max|g|: a few paths pass within rounding of a node and take the other
+cell.  On the short smile surface the same copy agrees to 1e-6.  No FP32 computation of
+the normals can do better than exact rounding, so the bar for FP32 on such workloads is
+the block-paired one of tests/fp32_checks.py.
+
+The second half pins lvo_path_state_bound (oracle.path_state_bound): every state of
+copies that compute in single precision -- the state rounded to float32 after each step,
+and in addition the normals by Box-Muller with every operation rounded to float32 and
+the vols rounded -- lies within the bound, path by path and step by step; planted
+mistakes in the bound (no step-derivative factor, no increment error) are caught.
+Every copy is planted in a copy of the oracle source, never in the oracle itself.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+STEP = "        w->z[n] = lvo_normal(pb->seed, p, n);\n        double s = w->iv[n].sigma;\n"
+STATE = "w->y[n + 1] = w->y[n] + (pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n];"
+STATE32 = "w->y[n + 1] = (double)(float)(w->y[n] + (pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n]);"
+ROUNDED = ("        w->z[n] = (double)(float)lvo_normal(pb->seed, p, n);\n"
+           "        double s = (double)(float)w->iv[n].sigma;\n        w->iv[n].sigma = s;\n")
+PER_OP = ("        w->z[n] = lvo_normal_f32(pb->seed, p, n);\n"
+          "        double s = (double)(float)w->iv[n].sigma;\n        w->iv[n].sigma = s;\n")
+NORMAL_F32 = '''static double lvo_normal_f32(uint64_t seed, uint64_t p, int64_t n)
+{
+    uint32_t w[4];
+    lvo_philox_words(seed, (uint64_t)(n / 4), p, w);
+    int r = (int)(n % 4), pair = r / 2;
+    float ua = (float)lvo_uniform(w[2 * pair]), ub = (float)lvo_uniform(w[2 * pair + 1]);
+    float l2 = (float)log2((double)ua);
+    float rad = (float)sqrt((double)(-1.38629436f * l2));
+    float c = (float)(r % 2 == 0 ? cos(2.0 * LVO_PI * (double)ub) : sin(2.0 * LVO_PI * (double)ub));
+    return (double)(rad * c);
+}
+
+/* Normals Z_n of paths'''
+BOUND = "        e[n + 1] = jn * e[n] + u * (ks *"
+
+
+def _copy(tmp, name, *edits):
+    src = open(oracle.SOURCE).read()
+    for old, new in edits:
+        assert src.count(old) == 1, old
+        src = src.replace(old, new)
+    path = os.path.join(tmp, f"{name}.c")
+    with open(path, "w") as f:
+        f.write(src)
+    return oracle.Oracle(oracle.build(path, os.path.join(tmp, f"lib{name}.so")))
+
+
+@pytest.fixture(scope="module")
+def copies(tmp_path_factory):
+    d = str(tmp_path_factory.mktemp("fp32copies"))
+    return dict(
+        rounded=_copy(d, "rounded", (STEP, ROUNDED)),
+        state32=_copy(d, "state32", (STATE, STATE32)),
+        all32=_copy(d, "all32", (STEP, PER_OP), (STATE, STATE32), ("/* Normals Z_n of paths", NORMAL_F32)),
+        no_jacobian=_copy(d, "no_jacobian", (BOUND, "        e[n + 1] = e[n] + u * (ks *")),
+    )
+
+
+def test_exactly_rounded_single_precision_misses_the_strict_bar_on_long_horizons(copies):
+    o = oracle.default()
+    s = W.wide_surface(1).rounded_to_f32()
+    a = o.price_and_grad(s, W.call(100.0, 5.0), 1 << 18, 260)
+    b = copies["rounded"].price_and_grad(s, W.call(100.0, 5.0), 1 << 18, 260)
+    gmax = np.abs(a["grad"]).max()
+    err = np.abs(a["grad"] - b["grad"])
+    assert abs(a["price"][0] - b["price"][0]) < 1e-5 * 100.0
+    assert err.max() > 5 * 1e-4 * gmax, err.max() / gmax
+    assert np.mean(err > 1e-4 * gmax) > 0.01
+    wl = W.small_call()
+    s = wl.surface.rounded_to_f32()
+    a = o.price_and_grad(s, wl.book, wl.n_paths, wl.n_steps)
+    b = copies["rounded"].price_and_grad(s, wl.book, wl.n_paths, wl.n_steps)
+    assert np.abs(a["grad"] - b["grad"]).max() < 1e-6 * np.abs(a["grad"]).max()
+
+
+def _worst_ratio(orc, copy, surface, book, N, paths, model=None):
+    worst = 0.0
+    for p in paths:
+        y = orc.path(surface, book, N, 0, int(p))["y"]
+        y2 = copy.path(surface, book, N, 0, int(p))["y"]
+        e, _ = orc.path_state_bound(surface, book, N, 0, int(p), model=model)
+        worst = max(worst, float((np.abs(y2 - y)[1:] / e[1:]).max()))
+    return worst
+
+
+CASES = [("benchmark 60x30 log axis", W.book_surface(0), W.call(100.0, 3.0), 156, (13366,)),
+         ("100x50 linear axis, 5y", W.wide_surface(1), W.call(100.0, 5.0), 260, ())]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_state_bound_holds_for_single_precision_copies(copies, case):
+    _, s, book, N, extra = case
+    s = s.rounded_to_f32()
+    paths = list(range(0, 600)) + list(extra)
+    o = oracle.default()
+    for name in ("state32", "all32"):
+        r = _worst_ratio(o, copies[name], s, book, N, paths)
+        assert r <= 0.6, (name, r)
+    # not vacuous: the bound is a few 1e-6 in y for a typical path
+    e_last = [o.path_state_bound(s, book, N, 0, p)[0][-1] for p in range(0, 200)]
+    assert np.median(e_last) < 1e-5
+
+
+def _heaviest(orc, surface, book, N, n_scan=20000, k=20):
+    """The k paths among the first n_scan whose bound grows most: those with the largest
+    step-derivative products, where the state is most sensitive to rounding."""
+    e_last = np.array([orc.path_state_bound(surface, book, N, 0, p)[0][-1] for p in range(n_scan)])
+    return np.argsort(e_last)[-k:]
+
+
+def test_state_bound_mutants_are_caught(copies):
+    """On the long-horizon surface's most sensitive paths, the bound without the step
+    derivatives, or without the increment's own error, is broken by a single-precision
+    copy, while the bound itself holds with room."""
+    _, s, book, N, _ = CASES[1]
+    s = s.rounded_to_f32()
+    o = oracle.default()
+    heavy = _heaviest(o, s, book, N)
+    assert _worst_ratio(o, copies["state32"], s, book, N, heavy) <= 0.6
+    assert _worst_ratio(o, copies["all32"], s, book, N, heavy) <= 0.6
+    # every step derivative taken as 1
+    worst = 0.0
+    for p in heavy:
+        y = o.path(s, book, N, 0, int(p))["y"]
+        y2 = copies["state32"].path(s, book, N, 0, int(p))["y"]
+        e, _ = copies["no_jacobian"].path_state_bound(s, book, N, 0, int(p))
+        worst = max(worst, float((np.abs(y2 - y)[1:] / e[1:]).max()))
+    assert worst > 1.0, worst
+    # no error in the increment (k_step = 0): the single-precision normals break it
+    r = _worst_ratio(o, copies["all32"], s, book, N, heavy, model=(2.0 ** -24, 0.0, 8.0, 4.0))
+    assert r > 1.0, r

@@ -14,7 +14,7 @@ import oracle
 from tests import pins
 
 MUTANTS = {
-    "drift_dropped": ("w->y[n] - 0.5 * s * s * dt + s * sdt * w->z[n]", "w->y[n] + s * sdt * w->z[n]"),
+    "drift_dropped": ("w->y[n] + (pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n]", "w->y[n] + pb->rate * dt + s * sdt * w->z[n]"),
     "sqrt_dt_wrong": ("pb->sqrt_dt = sqrt(pb->dt);", "pb->sqrt_dt = pb->dt;"),
     "box_muller_sin_cos_swapped": ("if (r % 2 == 0)\n        return radius * cos", "if (r % 2 == 1)\n        return radius * cos"),
     "uniform_not_centred": ("+ 0.5) / 8388608.0", "+ 0.0) / 8388608.0"),
@@ -31,9 +31,9 @@ MUTANTS = {
     "adjoint_no_spot_slope": ("lam = lam * (1.0 + c * iv->dsigma_dy);", "lam = lam * 1.0;"),
     "adjoint_wrong_node": ("grad[iv->i * J + iv->j + 1] += gbar * iv->w[2];", "grad[(iv->i + 1) * J + iv->j + 1] += gbar * iv->w[2];"),
     "put_derivative_sign": ("if (pb->is_put[k]) return K > S ? -S : 0.0;", "if (pb->is_put[k]) return K > S ? S : 0.0;"),
-    "payoff_at_last_step": ("payoffs[k] = lvo_payoff(pb, k, w->y[pb->tap_step[k]]);", "payoffs[k] = lvo_payoff(pb, k, w->y[N]);"),
+    "payoff_at_last_step": ("payoffs[k] = pb->disc[k] * lvo_payoff(pb, k, w->y[pb->tap_step[k]]);", "payoffs[k] = pb->disc[k] * lvo_payoff(pb, k, w->y[N]);"),
     "cotangent_weight_ignored": ("double wk = pb->weight ? pb->weight[k] : 1.0;", "double wk = 1.0;"),
-    "euler_x_lognormal_step": ("X[n + 1] = X[n] + w->iv[n].sigma * X[n] * sdt * w->z[n];",
+    "euler_x_lognormal_step": ("X[n + 1] = X[n] + pb->rate * X[n] * dt + w->iv[n].sigma * X[n] * sdt * w->z[n];",
                                "X[n + 1] = X[n] * exp(w->iv[n].sigma * sdt * w->z[n] - 0.5 * w->iv[n].sigma * w->iv[n].sigma * dt);"),
     "euler_x_c_without_X": ("double c = X[n - 1] * sdt * w->z[n - 1];", "double c = sdt * w->z[n - 1];"),
     "euler_x_no_spot_slope": ("(iv->sigma + iv->dsigma_dy)", "(iv->sigma)"),
@@ -42,12 +42,20 @@ MUTANTS = {
     "bf16_ties_away": ("else pick = (below & 0x10000u) ? above : below;", "else pick = above;"),
     "bf16_ties_odd": ("else pick = (below & 0x10000u) ? above : below;", "else pick = (below & 0x10000u) ? below : above;"),
     "bf16_straight_from_double": ("const double x = (double)lvo_bits_to_float(mag);", "const double x = fabs(v);"),
+    "rate_drift_sign": ("(pb->rate - 0.5 * s * s) * dt", "(-pb->rate - 0.5 * s * s) * dt"),
+    "rate_in_the_diffusion": ("(pb->rate - 0.5 * s * s) * dt + s * sdt * w->z[n]", "(-0.5 * s * s) * dt + (s + pb->rate) * sdt * w->z[n]"),
+    "rate_not_discounted": ("pb->disc[k] = exp(-pb->rate * pb->maturity[k]);", "pb->disc[k] = 1.0;"),
+    "rate_discount_at_last_maturity": ("pb->disc[k] = exp(-pb->rate * pb->maturity[k]);", "pb->disc[k] = exp(-pb->rate * pb->dt * pb->n_steps);"),
+    "rate_seed_undiscounted": ("lam += wk * pb->disc[k] * lvo_dpayoff_dy(pb, k, w->y[n]);", "lam += wk * lvo_dpayoff_dy(pb, k, w->y[n]);"),
+    "rate_euler_x_trend_missing": ("X[n + 1] = X[n] + pb->rate * X[n] * dt + w->iv[n].sigma", "X[n + 1] = X[n] + w->iv[n].sigma"),
+    "rate_euler_x_jacobian_without_trend": ("lam * (1.0 + pb->rate * dt + sdt", "lam * (1.0 + sdt"),
 }
 
 BATTERY = [pins.pin_round_bf16, pins.pin_uniform, pins.pin_box_muller, pins.pin_interp, pins.pin_flat_pathwise_vega,
            pins.pin_one_step, pins.pin_adjoint_fd, pins.pin_put_call_parity,
            pins.pin_flat_black_scholes, pins.pin_term_structure, pins.pin_euler_x_one_step,
-           pins.pin_euler_x_moments]
+           pins.pin_euler_x_moments, pins.pin_rate_adjoint_fd, pins.pin_rate_parity_and_martingale,
+           pins.pin_rate_one_step, pins.pin_rate_euler_x_one_step, pins.pin_rate_black_scholes]
 
 
 def _build_mutant(name, old, new, tmpdir):

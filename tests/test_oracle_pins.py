@@ -20,7 +20,8 @@ def test_philox_matches_rocrand(orc):
     pins.pin_flat_pathwise_vega, pins.pin_flat_vega_and_columns, pins.pin_term_structure,
     pins.pin_put_call_parity, pins.pin_threads, pins.pin_one_step, pins.pin_two_steps,
     pins.pin_adjoint_fd, pins.pin_zero_buckets, pins.pin_euler_x_one_step, pins.pin_euler_x_moments,
-    pins.pin_round_bf16,
+    pins.pin_round_bf16, pins.pin_rate_black_scholes, pins.pin_rate_parity_and_martingale,
+    pins.pin_rate_one_step, pins.pin_rate_euler_x_one_step, pins.pin_rate_adjoint_fd,
 ], ids=lambda f: f.__name__)
 def test_pin(orc, pin):
     pin(orc)
