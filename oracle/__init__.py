@@ -230,8 +230,10 @@ class Oracle:
 # Unit roundoff of IEEE single precision; the local error of one step's increment and
 # of the cell coordinate, in units of it (hardware log/sqrt/sin/cos and exp of a few
 # ulps each, a handful of rounded products and sums); the safety margin on the
-# coordinate.
-FP32_MODEL = (2.0 ** -24, 8.0, 8.0, 4.0)
+# coordinate; the absolute error of a normal in units of u and of its Box-Muller
+# radius (the hardware sine and cosine are accurate to an absolute, not a relative,
+# error near their zeros).
+FP32_MODEL = (2.0 ** -24, 8.0, 8.0, 4.0, 16.0)
 
 _default: Optional[Oracle] = None
 

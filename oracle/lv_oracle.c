@@ -623,14 +623,17 @@ double lvo_round_bf16(double v)
 /* d sigma_n, s'_n = d sigma / d y at the step: the factors of the adjoint    */
 /* recursion).  To first order the state error is bounded by the running sum  */
 /*   e_0 = 0,   e_{n+1} = |J_n| e_n + rho_n,                                 */
-/*   rho_n = u (k_step (|sigma_n sqrt(dt) Z_n| + sigma_n^2 dt / 2) + |y_{n+1}|) */
-/* -- the increment computed with relative error k_step u, the new state      */
-/* rounded -- with u the unit roundoff.  The grid coordinate a_n is then      */
+/*   rho_n = u (k_step (|sigma_n sqrt(dt) Z_n| + sigma_n^2 dt / 2)             */
+/*              + k_abs sigma_n sqrt(dt) R_n + |y_{n+1}|)                      */
+/* -- the increment computed with relative error k_step u, the normal also    */
+/* with an absolute error k_abs u R_n (R_n the Box-Muller radius of its pair: */
+/* near the zeros of sine and cosine their error is absolute, not relative), */
+/* the new state rounded -- with u the unit roundoff.  The coordinate a_n is  */
 /* known to within da_n = M (|da/dy| e_n + k_coord u (|a_n| + S_n / du on a    */
 /* linear axis)), M a safety margin; where the nearest spot node lies within  */
 /* da_n of a_n the step's cell is undecided at that precision (the slope of   */
 /* the bilinear surface jumps there) and |J_n| takes its largest value over   */
-/* the cells at the node.  model = {u, k_step, k_coord, M}; e[N+1];           */
+/* the cells at the node.  model = {u, k_step, k_coord, M, k_abs}; e[N+1];    */
 /* undecided[N].                                                              */
 /* ------------------------------------------------------------------------- */
 static double lvo_cell_slope_dy(const lvo_problem *pb, int c, double t, double S, double du)
@@ -655,7 +658,7 @@ int lvo_path_state_bound(int32_t n_spot, int32_t spot_kind, double spot_lo, doub
     lvo_problem pb = {n_spot, spot_kind, spot_lo, spot_hi, n_time, time_lo, time_hi, sigma,
                       spot, n_opt, is_put, strike, maturity, weight, n_steps, seed, 0, rate, 0, 0, NULL, NULL};
     if (lvo_setup(&pb) != 0) return -1;
-    const double u = model[0], ks = model[1], kc = model[2], M = model[3];
+    const double u = model[0], ks = model[1], kc = model[2], M = model[3], ka = model[4];
     lvo_work w;
     lvo_work_alloc(&w, n_steps);
     double *pay = (double *)malloc(sizeof(double) * n_opt);
@@ -682,8 +685,10 @@ int lvo_path_state_bound(int32_t n_spot, int32_t spot_kind, double spot_lo, doub
             jn = fmax(jn, fabs(1.0 + c * lvo_cell_slope_dy(&pb, kn - 1, n * dt, S, du)));
             jn = fmax(jn, fabs(1.0 + c * lvo_cell_slope_dy(&pb, kn, n * dt, S, du)));
         }
+        const double zp = lvo_normal(seed, (uint64_t)p, n ^ 1);   /* the other normal of the pair */
+        const double radius = sqrt(w.z[n] * w.z[n] + zp * zp);
         e[n + 1] = jn * e[n] + u * (ks * (fabs(iv->sigma * sdt * w.z[n]) + 0.5 * iv->sigma * iv->sigma * dt) +
-                                    fabs(w.y[n + 1]));
+                                    ka * iv->sigma * sdt * radius + fabs(w.y[n + 1]));
     }
     free(pay);
     lvo_work_free(&w);

@@ -141,6 +141,6 @@ def test_state_bound_mutants_are_caught(copies):
         e, _ = copies["no_jacobian"].path_state_bound(s, book, N, 0, int(p))
         worst = max(worst, float((np.abs(y2 - y)[1:] / e[1:]).max()))
     assert worst > 1.0, worst
-    # no error in the increment (k_step = 0): the single-precision normals break it
-    r = _worst_ratio(o, copies["all32"], s, book, N, heavy, model=(2.0 ** -24, 0.0, 8.0, 4.0))
+    # no error in the increment (k_step = k_abs = 0): the single-precision normals break it
+    r = _worst_ratio(o, copies["all32"], s, book, N, heavy, model=(2.0 ** -24, 0.0, 8.0, 4.0, 0.0))
     assert r > 1.0, r
