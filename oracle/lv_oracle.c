@@ -624,13 +624,17 @@ double lvo_round_bf16(double v)
 /* recursion).  To first order the state error is bounded by the running sum  */
 /*   e_0 = 0,   e_{n+1} = |J_n| e_n + rho_n,                                 */
 /*   rho_n = u (k_step (|sigma_n sqrt(dt) Z_n| + sigma_n^2 dt / 2)             */
-/*              + k_abs sigma_n sqrt(dt) R_n + |y_{n+1}|)                      */
+/*              + k_abs sigma_n sqrt(dt) R_n + |y_{n+1}|) + |c_n s'_n| cy_n    */
 /* -- the increment computed with relative error k_step u, the normal also    */
 /* with an absolute error k_abs u R_n (R_n the Box-Muller radius of its pair: */
 /* near the zeros of sine and cosine their error is absolute, not relative), */
-/* the new state rounded -- with u the unit roundoff.  The coordinate a_n is  */
+/* the new state rounded, and sigma_n read at a coordinate off by cy_n (the   */
+/* coordinate's own rounding below, in units of y) -- with u the unit        */
+/* roundoff.  The coordinate a_n is                                           */
 /* known to within da_n = M (|da/dy| e_n + k_coord u (|a_n| + S_n / du on a    */
-/* linear axis)), M a safety margin; where the nearest spot node lies within  */
+/* linear axis)), the second term (cy_n = that term / |da/dy|) being the      */
+/* rounding of the coordinate itself (on a linear axis it comes with          */
+/* S = X0 e^y), M a safety margin; where the nearest spot node lies within    */
 /* da_n of a_n the step's cell is undecided at that precision (the slope of   */
 /* the bilinear surface jumps there) and |J_n| takes its largest value over   */
 /* the cells at the node.  model = {u, k_step, k_coord, M, k_abs}; e[N+1];    */
@@ -672,8 +676,9 @@ int lvo_path_state_bound(int32_t n_spot, int32_t spot_kind, double spot_lo, doub
         const lvo_interp *iv = &w.iv[n];
         const double S = spot * exp(w.y[n]);
         const double a = ((spot_kind == 0 ? S : log(S)) - u0) / du;
-        const double da = M * ((spot_kind == 0 ? S / du : 1.0 / du) * e[n] +
-                               kc * u * (fabs(a) + (spot_kind == 0 ? S / du : 0.0)));
+        const double dady = spot_kind == 0 ? S / du : 1.0 / du;
+        const double coord = kc * u * (fabs(a) + (spot_kind == 0 ? S / du : 0.0));   /* cells */
+        const double da = M * (dady * e[n] + coord);
         const double c = -iv->sigma * dt + sdt * w.z[n];
         double jn = fabs(1.0 + c * iv->dsigma_dy);
         double k = floor(a + 0.5);
@@ -688,7 +693,8 @@ int lvo_path_state_bound(int32_t n_spot, int32_t spot_kind, double spot_lo, doub
         const double zp = lvo_normal(seed, (uint64_t)p, n ^ 1);   /* the other normal of the pair */
         const double radius = sqrt(w.z[n] * w.z[n] + zp * zp);
         e[n + 1] = jn * e[n] + u * (ks * (fabs(iv->sigma * sdt * w.z[n]) + 0.5 * iv->sigma * iv->sigma * dt) +
-                                    ka * iv->sigma * sdt * radius + fabs(w.y[n + 1]));
+                                    ka * iv->sigma * sdt * radius + fabs(w.y[n + 1])) +
+                   fabs(c * iv->dsigma_dy) * coord / dady;
     }
     free(pay);
     lvo_work_free(&w);

@@ -197,3 +197,14 @@ def test_create_without_a_device_is_a_hip_error(lib):
     assert h.value is None
     assert b"device" in lib.lv_last_error(None)
     assert lv.check(**_req()) == _lib.LV_OK
+
+
+def test_rate_is_validated():
+    """A rate is any finite r with |r| <= 1 in every mode and scheme; NaN, inf or a larger
+    magnitude is an argument error."""
+    for adj in ("stored", "checkpoint", "none"):
+        for scheme in ("log_euler", "euler_x"):
+            assert lv.check(**_req(), rate=0.05, adjoint=adj, scheme=scheme) == _lib.LV_OK
+    assert lv.check(**_req(), rate=-1.0) == _lib.LV_OK
+    for bad in (float("nan"), float("inf"), 1.5, -2.0):
+        assert lv.check(**_req(), rate=bad) == _lib.LV_ERR_ARG

@@ -111,9 +111,10 @@ def test_state_bound_holds_for_single_precision_copies(copies, case):
     for name in ("state32", "all32"):
         r = _worst_ratio(o, copies[name], s, book, N, paths)
         assert r <= 0.6, (name, r)
-    # not vacuous: the bound is a few 1e-6 in y for a typical path
+    # not vacuous: for a typical path the bound at the last step is a few 1e-6 (log axis)
+    # to 1e-5 (linear axis, where the rounded exp of the spot moves sigma by its slope)
     e_last = [o.path_state_bound(s, book, N, 0, p)[0][-1] for p in range(0, 200)]
-    assert np.median(e_last) < 1e-5
+    assert np.median(e_last) < 3e-5
 
 
 def _heaviest(orc, surface, book, N, n_scan=20000, k=20):
@@ -141,6 +142,7 @@ def test_state_bound_mutants_are_caught(copies):
         e, _ = copies["no_jacobian"].path_state_bound(s, book, N, 0, int(p))
         worst = max(worst, float((np.abs(y2 - y)[1:] / e[1:]).max()))
     assert worst > 1.0, worst
-    # no error in the increment (k_step = k_abs = 0): the single-precision normals break it
-    r = _worst_ratio(o, copies["all32"], s, book, N, heavy, model=(2.0 ** -24, 0.0, 8.0, 4.0, 0.0))
+    # no error in the increment or the coordinate (k_step = k_abs = k_coord = 0): the
+    # single-precision normals break it
+    r = _worst_ratio(o, copies["all32"], s, book, N, heavy, model=(2.0 ** -24, 0.0, 0.0, 4.0, 0.0))
     assert r > 1.0, r

@@ -5,8 +5,13 @@ across paths in FP64):
   * Philox words: bit-exact.
   * price: |GPU - oracle| < 1e-5 * spot; std_err within 1e-4 relative.
   * gradient: every bucket within 1e-4 * max|g|; buckets the oracle leaves
-    exactly zero are exactly zero.
-  * the FP64 kernels: price within 1e-11 relative, buckets within 1e-9 * max|g|.
+    exactly zero are exactly zero.  On the noisy, fine or long-horizon surfaces,
+    where single precision cannot take some of the cell decisions the FP64 oracle
+    takes, the FP32 bars are those of tests/fp32_checks.py: FP32 states within the
+    oracle's single-precision bound path by path, and a bucket difference that is
+    unbiased block by block.
+  * the FP64 kernels: price within 1e-11 relative, buckets within 1e-9 * max|g|,
+    on every workload.
 The oracle sees the surface rounded to float32 when it checks the FP32 kernels,
 so that input rounding is not counted as error.
 """
@@ -19,6 +24,7 @@ import pytest
 
 import oracle
 import workloads as W
+from tests import fp32_checks as F
 
 pytestmark = pytest.mark.gpu
 
@@ -184,23 +190,24 @@ def test_large_grid(lv, ctx, orc, precision, adjoint):
     """A 150 x 80 grid with a call and a put on 2^17 + 5 paths and 104 steps against
     the oracle: the planner shrinks the histogram window (and the block) to fit the
     grid in LDS.  A 200 x 100 grid does not fit a block and is refused before any
-    launch.  FP32 bar: on this grid (about 50 nodes per unit of ln S) a few buckets
-    differ by up to 1.4e-4 of max|g|, the same at 2^13 and 2^17 paths and the same for
-    every block size, histogram scale and the checkpointed kernel, so it is the FP32
-    path arithmetic, not the accumulation: the FP32 cell coordinate flips a few states
-    to the neighbouring cell, and on this noisy grid a flipped path with a large adjoint
-    moves a bucket that much (test_fp32_node_flips reproduces it on the oracle).  Every
-    bucket within 3e-4 of max|g|, and all but 1% within the usual 1e-4."""
+    launch.  On this noisy grid (about 50 nodes per unit of ln S) a few FP32 paths
+    with large adjoints take the neighbouring cell at a node (test_fp32_node_flips
+    reproduces it on the oracle), so FP32 is held to the block-paired bar."""
     surf = large_grid()
     book = W.Book([0, 1], [100.0, 90.0], [2.0, 1.0], [1.0, 0.5])
     P, N = (1 << 17) + 5, 104
     s = surf.rounded_to_f32() if precision == 32 else surf
     ref = orc.price_and_grad(s, book, P, N, seed=13)
     got = gpu_run(lv, ctx, surf, book, P, N, 13, precision=precision, adjoint=adjoint)
-    assert_parity(got, ref, precision, f"150x80 {precision} {adjoint}", grad_tol=3e-4)
-    if precision == 32:
-        e = np.abs(got["grad"] - ref["grad"]) / np.abs(ref["grad"]).max()
-        assert np.mean(e > GRAD_TOL) <= 0.01, np.sort(e.ravel())[-20:]
+    if precision == 64:
+        assert_parity(got, ref, 64, f"150x80 {precision} {adjoint}")
+    else:
+        assert_parity(dict(got, grad=None, delta=None), ref, 32, f"150x80 FP32 {adjoint} prices")
+        info = ctx.run_info()
+        B, T = info["n_blocks"], info["tile_paths"]
+        blocks = ctx.block_grads(surf.sigma.size, book.n).reshape((B,) + surf.sigma.shape)
+        ob = F.oracle_block_sums(orc, s, book, P, N, 13, B, T)
+        F.paired_check(got["grad"], blocks, ob, P, f"150x80 FP32 {adjoint}")
     sa, ta = W.Axis(200, W.LOG, 20.0, 400.0), W.Axis(100, W.LIN, 0.0, 2.0)
     huge = W.Surface(sa, ta, np.full((200, 100), 0.2))
     with pytest.raises(lv.LVError, match="UNSUPPORTED"):
@@ -397,39 +404,38 @@ def test_block_shapes_agree(lv, ctx, orc):
 # --------------------------------------------------------------------------
 # batched surfaces, device API, graphs, autograd
 # --------------------------------------------------------------------------
-# The pathwise derivative of a bilinear surface jumps at spot nodes: where a path's
-# state lands within rounding of a node, the FP32 and FP64 computations can take
-# different sides and that path's lambda changes by a finite amount from then on.
-# On the noisy 100 x 50 surfaces over 260 steps these flips move single buckets by
-# up to ~1e-2 max|g| at a few thousand paths (the FP64 oracle with its state merely
-# rounded to float32 shows the same effect); the FP64 kernels carry the tight bar.
-FLIP_GRAD_TOL = 1e-2
-
-
 @pytest.mark.parametrize("precision", [64, 32])
 def test_surface_batch(lv, ctx, orc, precision):
+    """Three 100 x 50 surfaces on the same 4096 paths of 260 steps in one batch: FP64
+    against the oracle at the tight bar; FP32 prices against the oracle, each surface's
+    batch gradient equal to a single-surface call's, and that call's blocks paired
+    with the oracle's (the 5-year noisy linear-axis surfaces are where single
+    precision leaves cell decisions open)."""
     surfs = [W.wide_surface(s) for s in (1, 2, 3)]
     sig = np.stack([s.sigma for s in surfs])
     book = W.call(100.0, 5.0)
     P, N = 4096, 260
+    ax = dict(spot_axis=surfs[0].spot_axis, time_axis=surfs[0].time_axis)
     for adjoint in ("checkpoint", "stored"):
         say(f"  batch of 3 wide surfaces, {adjoint}, FP{precision}")
-        p, se, g, d = lv.price_and_grad_batch(sig, 100.0, book.strike, book.maturity, P, N, 0,
-                                              spot_axis=surfs[0].spot_axis,
-                                              time_axis=surfs[0].time_axis, adjoint=adjoint,
-                                              precision=precision, ctx=ctx)
+        p, se, g, d = lv.price_and_grad_batch(sig, 100.0, book.strike, book.maturity, P, N, 0, **ax,
+                                              adjoint=adjoint, precision=precision, ctx=ctx)
         for k, s in enumerate(surfs):
-            ref = orc.price_and_grad(s.rounded_to_f32() if precision == 32 else s, book, P, N)
+            s_ref = s.rounded_to_f32() if precision == 32 else s
+            ref = orc.price_and_grad(s_ref, book, P, N)
             got = dict(price=p[k], stderr=se[k], grad=g[k], delta=d[k])
             if precision == 64:
                 assert_parity(got, ref, 64, f"batch surface {k} {adjoint}")
                 continue
-            assert abs(p[k][0] - ref["price"][0]) < PRICE_TOL
-            gmax = np.abs(ref["grad"]).max()
-            err = np.abs(g[k] - ref["grad"])
-            say(f"  FP32 surface {k} {adjoint}: max bucket err/max|g| = {err.max() / gmax:.3g}, "
-                f"buckets within 1e-4: {np.mean(err <= 1e-4 * gmax):.4f}")
-            assert err.max() <= FLIP_GRAD_TOL * gmax
+            assert_parity(dict(got, grad=None, delta=None), ref, 32, f"batch surface {k} {adjoint} prices")
+            p1, s1, g1, d1 = lv.price_and_grad(s, 100.0, book.strike, book.maturity, P, N, 0, adjoint=adjoint,
+                                               ctx=ctx)
+            assert np.array_equal(g1, g[k]) and np.array_equal(p1, p[k])
+            info = ctx.run_info()
+            B, T = info["n_blocks"], info["tile_paths"]
+            blocks = ctx.block_grads(s.sigma.size).reshape((B,) + s.sigma.shape)
+            ob = F.oracle_block_sums(orc, s_ref, book, P, N, 0, B, T)
+            F.paired_check(g[k], blocks, ob, P, f"FP32 surface {k} {adjoint}")
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(adjoint="checkpoint"),
@@ -487,14 +493,6 @@ def test_autograd_split_matches_fused(lv, ctx):
 # --------------------------------------------------------------------------
 # full size, in the benchmark's launch configuration
 # --------------------------------------------------------------------------
-def batch_stderr(orc, surface, book, n_paths, n_steps, seed, n_batches=32):
-    """Per-bucket standard error of the gradient estimate by batch means (oracle)."""
-    per = n_paths // n_batches
-    gs = np.array([orc.sums(surface, book, n_steps, seed, [(b * per, (b + 1) * per)])["sum_grad"] / per
-                   for b in range(n_batches)])
-    return gs.std(axis=0, ddof=1) / math.sqrt(n_batches)
-
-
 def test_per_option_grads_sum_to_book(lv, ctx):
     """Per-option grids (one stored forward, one reverse per option with a one-hot
     cotangent) equal the fused call's grid with that option's weight alone, and add up,
@@ -574,47 +572,32 @@ def test_bump_and_reprice_rejects_bad_arguments(lv, ctx):
 
 
 def test_full_size_single_call_60x30(lv, ctx, orc):
-    """The benchmark workload at full size (2^19 paths, 156 steps, 60 x 30 grid) in the
-    benchmark's launch configuration.  FP64 kernels: the tight bar.  FP32 kernels:
-    price within 1e-5 spot; each bucket within 1e-4 max|g| or, for the rare buckets a
-    spot-node flip of one FP32 path moves further, within a quarter of that bucket's
-    Monte Carlo standard error (the FP32 error stays far below the statistical error
-    at equal paths).  Sampled per-block partial sums are checked one by one."""
+    """The 60 x 30 single-call workload at full size (2^19 paths, 156 steps) in the
+    benchmark's autotuned launch configuration.  FP64 kernels: the tight bar in both
+    adjoint modes.  FP32: price within 1e-5 spot, and the block-paired gradient bar
+    (every block's partial sums against the oracle's over the same paths)."""
     wl = W.single_call_60x30()
     s32 = wl.surface.rounded_to_f32()
     say(f"  full-size {wl.name}: oracle ({oracle.default_threads()} threads)")
     ref64 = orc.price_and_grad(wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed)
     ref32 = orc.price_and_grad(s32, wl.book, wl.n_paths, wl.n_steps, wl.seed)
-    se = batch_stderr(orc, s32, wl.book, wl.n_paths, wl.n_steps, wl.seed)
     for adjoint in ("stored", "checkpoint"):
         got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed,
                       precision=64, adjoint=adjoint)
         assert_parity(got, ref64, 64, f"{wl.name} FP64 {adjoint}")
-    got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed)
-    info = ctx.run_info()
-    blocks = ctx.block_grads(wl.surface.sigma.size)
-    assert abs(got["price"][0] - ref32["price"][0]) < PRICE_TOL
-    gmax = np.abs(ref32["grad"]).max()
-    err = np.abs(got["grad"] - ref32["grad"])
-    say(f"  {wl.name} FP32: max err/max|g| {err.max() / gmax:.3g}, max err/stderr "
-        f"{(err / np.maximum(se, 1e-300)).max():.3g}, buckets within 1e-4 max|g|: "
-        f"{np.mean(err <= GRAD_TOL * gmax):.4f}")
-    assert np.all((err <= GRAD_TOL * gmax) | (err <= 0.25 * se))
-    assert np.all(got["grad"][ref32["grad"] == 0.0] == 0.0)
-    # sampled block partials: block b covered tiles b, b + B, ...; the sum over n_b
-    # paths has standard error se * sqrt(P n_b)
-    B, T = info["n_blocks"], info["tile_paths"]
-    n_tiles = (wl.n_paths + T - 1) // T
-    sampled = (0, 1, B // 2, B - 1)
-    ranges = {b: [(t * T, min((t + 1) * T, wl.n_paths)) for t in range(b, n_tiles, B)] for b in sampled}
-    for b in sampled:
-        r = orc.sums(s32, wl.book, wl.n_steps, wl.seed, ranges[b])
-        n_b = sum(e - a for a, e in ranges[b])
-        gb = blocks[b].reshape(wl.surface.sigma.shape)
-        scale = np.abs(r["sum_grad"]).max()
-        e = np.abs(gb - r["sum_grad"])
-        say(f"  FP32 block {b}: max err / max|partial| {e.max() / scale:.3g}")
-        assert np.all((e <= GRAD_TOL * scale) | (e <= 0.25 * se * math.sqrt(wl.n_paths * n_b))), f"block {b}"
+    for adjoint in ("stored", "checkpoint"):
+        got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed, adjoint=adjoint,
+                      autotune=True)
+        info = ctx.run_info()
+        assert abs(got["price"][0] - ref32["price"][0]) < PRICE_TOL
+        assert np.allclose(got["stderr"], ref32["stderr"], rtol=1e-4)
+        B, T = info["n_blocks"], info["tile_paths"]
+        blocks = ctx.block_grads(wl.surface.sigma.size).reshape((B,) + wl.surface.sigma.shape)
+        say(f"  {wl.name} FP32 {adjoint}: oracle sums over the paths of {B} blocks of tiles of {T}")
+        ob = F.oracle_block_sums(orc, s32, wl.book, wl.n_paths, wl.n_steps, wl.seed, B, T)
+        assert np.allclose(ob.sum(axis=0) / wl.n_paths, ref32["grad"], rtol=0,
+                           atol=1e-12 * np.abs(ref32["grad"]).max())
+        F.paired_check(got["grad"], blocks, ob, wl.n_paths, f"{wl.name} FP32 {adjoint}")
     got = gpu_run(lv, ctx, wl.surface, wl.book, wl.n_paths, wl.n_steps, wl.seed, precision=64)
     blocks = ctx.block_grads(wl.surface.sigma.size)
     # the FP64 kernels run a launch shape of their own (at most 512 lanes per block)
@@ -667,39 +650,28 @@ def test_autotune_picks_a_candidate(lv, ctx, orc):
     assert np.array_equal(got2["grad"], got["grad"])
 
 
-def check_fp32_grad(got_grad, ref_grad, se, what, tol_se=0.25, frac_1se=None):
-    """Every bucket within 1e-4 max|g| or within tol_se standard errors; optionally a
-    fraction of buckets within one standard error; exact zeros match."""
-    gmax = np.abs(ref_grad).max()
-    err = np.abs(got_grad - ref_grad)
-    ok = (err <= GRAD_TOL * gmax) | (err <= tol_se * se)
-    say(f"  {what}: max err/max|g| {err.max() / gmax:.3g}, within 1e-4 max|g|: "
-        f"{np.mean(err <= GRAD_TOL * gmax):.4f}, within 1 stderr: {np.mean(err <= se):.4f}, "
-        f"worst err/stderr outside 1e-4 max|g|: "
-        f"{(err / np.maximum(se, 1e-300))[err > GRAD_TOL * gmax].max(initial=0):.3g}")
-    assert np.all(ok), what
-    if frac_1se is not None:
-        assert np.mean((err <= se) | (err <= GRAD_TOL * gmax)) >= frac_1se, what
-    assert np.all(got_grad[ref_grad == 0.0] == 0.0), what
-
-
 def test_full_size_book64(lv, ctx, orc):
     """64 calls/puts of uneven maturity on one set of 2^20 paths, 156 steps, 60 x 30 grid:
-    the fused persistent (checkpoint) kernel, autotuned and graph-captured."""
+    the fused persistent (checkpoint) kernel and the stored-state pair, autotuned and
+    graph-captured.  FP32: prices within 1e-5 spot, block-paired gradient bar; FP64:
+    the tight bar."""
     wl = W.book_60x30()
     b = wl.book
     s32 = wl.surface.rounded_to_f32()
     say(f"  {wl.name}: oracle")
     ref32 = orc.price_and_grad(s32, b, wl.n_paths, wl.n_steps, wl.seed)
-    se = batch_stderr(orc, s32, b, wl.n_paths, wl.n_steps, wl.seed)
     for adjoint in ("checkpoint", "stored"):
         got = gpu_run(lv, ctx, wl.surface, b, wl.n_paths, wl.n_steps, wl.seed, adjoint=adjoint,
                       autotune=True, use_graph=True)
         dp = np.abs(got["price"] - ref32["price"]).max()
-        say(f"  book FP32 {adjoint}: max |dprice| over 64 options {dp:.3g}; launch {ctx.run_info()}")
+        info = ctx.run_info()
+        say(f"  book FP32 {adjoint}: max |dprice| over 64 options {dp:.3g}; launch {info}")
         assert dp < PRICE_TOL
         assert np.allclose(got["stderr"], ref32["stderr"], rtol=1e-4, atol=1e-9)
-        check_fp32_grad(got["grad"], ref32["grad"], se, f"book FP32 {adjoint}")
+        B, T = info["n_blocks"], info["tile_paths"]
+        blocks = ctx.block_grads(wl.surface.sigma.size, b.n).reshape((B,) + wl.surface.sigma.shape)
+        ob = F.oracle_block_sums(orc, s32, b, wl.n_paths, wl.n_steps, wl.seed, B, T)
+        F.paired_check(got["grad"], blocks, ob, wl.n_paths, f"book FP32 {adjoint}")
     ref64 = orc.price_and_grad(wl.surface, b, wl.n_paths, wl.n_steps, wl.seed)
     got = gpu_run(lv, ctx, wl.surface, b, wl.n_paths, wl.n_steps, wl.seed, precision=64, adjoint="checkpoint")
     assert_parity(got, ref64, 64, "book FP64 checkpoint")
@@ -728,10 +700,10 @@ def test_full_size_precision_study(lv, ctx, orc):
 
 
 def test_full_size_surface_batch(lv, ctx, orc):
-    """32 perturbed 100 x 50 surfaces, 2^24 paths, 260 steps, checkpointed adjoint.
-    FP32 against the FP64 kernels on the first and last surface; the FP64 kernels
-    against the oracle on sampled blocks of the last surface; FP32 payoff sums of
-    sampled blocks against the oracle."""
+    """32 perturbed 100 x 50 surfaces, 2^24 paths, 260 steps, checkpointed adjoint, in
+    the benchmark's launch: FP32 payoff sums of sampled blocks of the last surface
+    against the oracle, the FP64 kernels' price there, and their gradient partials on
+    sampled blocks against the oracle at the tight bar."""
     wl = W.surface_batch()
     sig = np.stack([s.sigma for s in wl.surfaces])
     b = wl.book
@@ -752,29 +724,16 @@ def test_full_size_surface_batch(lv, ctx, orc):
         dp = abs(part32["sum_pay"][blk, 0] - r["sum_pay"][0]) / n_b
         say(f"  FP32 block {blk}: payoff mean differs by {dp:.3g}")
         assert dp < PRICE_TOL
-    # FP32 against the FP64 kernels on the same paths.  Over five years of weekly
-    # steps on these noisy linear-axis surfaces the FP32 pathwise adjoint is far
-    # more flip-prone than on the benchmark workload (the FP64 oracle with its state
-    # merely rounded to float32 moves single buckets by up to 0.45 standard errors
-    # at 2^18 paths, and the flips' tail is heavy): the FP32 bar here is a
-    # characterisation, 99% of buckets within one standard error and none beyond
-    # ten, the standard error at 2^24 paths estimated from 16 independent FP64 runs
-    # of 2^22 paths (seeds 101..116).  The FP64 kernels carry the tight bar below.
-    for k in (0, len(wl.surfaces) - 1):
-        s = wl.surfaces[k]
-        say(f"  surface {k}: FP64 on the GPU")
-        p64, s64, g64, d64 = lv.price_and_grad(s, 100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps,
-                                               0, precision=64, adjoint="checkpoint", ctx=ctx)
-        assert abs(p[k][0] - p64[0]) < PRICE_TOL
-        assert abs(se_[k][0] / s64[0] - 1) < 1e-4
-        if k == len(wl.surfaces) - 1:     # keep the last surface's FP64 block partials
-            part64 = ctx.block_partials(1, sig[0].size)
-            info64 = ctx.run_info()
-        runs = np.array([lv.price_and_grad(s, 100.0, b.strike, b.maturity, 1 << 22, wl.n_steps, seed,
-                                           precision=64, adjoint="checkpoint", ctx=ctx)[2]
-                         for seed in range(101, 117)])
-        se_full = runs.std(axis=0, ddof=1) * math.sqrt((1 << 22) / wl.n_paths)
-        check_fp32_grad(g[k], g64, se_full, f"surface {k} FP32 vs FP64 GPU", tol_se=10.0, frac_1se=0.99)
+    # the FP64 kernels on the last surface (their block partials are checked below);
+    # the FP32 gradient against the oracle is test_gpu_fp32_accuracy's
+    s = last
+    say("  last surface: FP64 on the GPU")
+    p64, s64, g64, d64 = lv.price_and_grad(s, 100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps,
+                                           0, precision=64, adjoint="checkpoint", ctx=ctx)
+    assert abs(p[-1][0] - p64[0]) < PRICE_TOL
+    assert abs(se_[-1][0] / s64[0] - 1) < 1e-4
+    part64 = ctx.block_partials(1, sig[0].size)
+    info64 = ctx.run_info()
     # the FP64 kernel against the oracle on sampled blocks of the last surface
     B, T = info64["n_blocks"], info64["tile_paths"]
     n_tiles = (wl.n_paths + T - 1) // T
