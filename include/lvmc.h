@@ -5,9 +5,12 @@
  *
  * Method (arXiv 2002.02481, "Sensitivity Analysis in the Dupire Local
  * Volatility Model with Tensorflow"):
- *   - the asset follows dX/X = sigma(X,t) dW with zero rates (Sec. IV-A, the SDE);
+ *   - the asset follows dX/X = sigma(X,t) dW (Sec. IV-A, the SDE), or with a
+ *     constant short rate r (lv_opts.rate) dX/X = r dt + sigma(X,t) dW, the
+ *     deterministic trend of the step Sec. IV-A narrates, payoffs discounted by
+ *     e^{-r T}; r = 0 (the default) is the paper's driftless SDE;
  *   - an explicit Euler scheme (Sec. IV-A) on y = ln(X/X0) with Ito drift:
- *       y_{n+1} = y_n - sigma_n^2 dt / 2 + sigma_n sqrt(dt) Z_n,  y_0 = 0,
+ *       y_{n+1} = y_n + (r - sigma_n^2 / 2) dt + sigma_n sqrt(dt) Z_n,  y_0 = 0,
  *     with sigma_n = sigma(X0 e^{y_n}, n dt) read at the left end of the step;
  *   - sigma(S,t) is bilinear in the nodes of a grid {(i dx, j dt)} (Sec. IV-A,
  *     the grid definition; Sec. IV-D, bilinear interpolation), linear in the
@@ -19,8 +22,8 @@
  *     Z_{4m+2} = r(w2) cos(2 pi u(w3)),  Z_{4m+3} = r(w2) sin(2 pi u(w3)),
  *     r(w) = sqrt(-2 ln u(w));
  *   - European call/put payoffs at each option's maturity, averaged over
- *     paths (Sec. IV-B, IV-C): price_k = mean_p payoff_k, std_err_k =
- *     sqrt(sample variance / P);
+ *     paths (Sec. IV-B, IV-C): price_k = e^{-r T_k} mean_p payoff_k, std_err_k =
+ *     sqrt(sample variance / P) of the discounted payoff;
  *   - the gradient of the weighted book value sum_k w_k price_k with respect to
  *     every vol node by reverse-mode differentiation of the simulation
  *     (Sec. III, Sec. IV-C), i.e. the average over paths of each path's
@@ -137,6 +140,11 @@ typedef struct {
                                gradients are then those of the rounded surface, the gradient
                                being taken with respect to its nodes.  0 (default): sigma as
                                given; any other value is LV_ERR_ARG */
+    double rate;            /* constant short rate r (per year, continuously compounded): each step
+                               adds the trend r dt to ln X (r dt X to X on the Euler step on X),
+                               and every price, standard error, gradient and delta is discounted
+                               by e^{-r T_k} of its option; 0 (default) = the driftless SDE.
+                               Finite with |r| <= 1, else LV_ERR_ARG */
 } lv_opts;
 
 enum { LV_SCHEME_LOG_EULER = 0, LV_SCHEME_EULER_X = 1 };
@@ -234,11 +242,11 @@ lv_status lv_states_bytes(int32_t precision, int64_t n_paths, int32_t n_steps, s
 
 /* Split forward (for autograd): simulate, write every state into states_dev
  * (device, caller-owned, lv_states_bytes long) and per-option price and
- * std_err (device [n_opt] FP64).  Asynchronous on the context's stream.
- * The book's weights are ignored here. */
+ * std_err (device [n_opt] FP64), log-Euler with rate `rate` (as lv_opts.rate).
+ * Asynchronous on the context's stream.  The book's weights are ignored here. */
 lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
                          const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
-                         int32_t precision, void *states_dev, double *price_dev,
+                         int32_t precision, double rate, void *states_dev, double *price_dev,
                          double *std_err_dev);
 
 /* Split backward: from the states of lv_forward_dev (same arguments) and a
@@ -247,8 +255,23 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
  * Asynchronous on the context's stream.  The book's weights are ignored. */
 lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
                           const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
-                          int32_t precision, const void *states_dev, const double *cotangent_dev,
-                          double *grad_dev, double *delta_dev);
+                          int32_t precision, double rate, const void *states_dev,
+                          const double *cotangent_dev, double *grad_dev, double *delta_dev);
+
+/* Per-option vol-grid gradients from one simulation (Sec. III, Sec. IV-C: the
+ * sensitivities of every price of a book, not only of a weighted sum): from the
+ * states of lv_forward_dev (same arguments; log-Euler, rate as there), write
+ * grads_dev [n_opt][I*J] = d price_k / d sigma for every option k (caller order)
+ * and, if non-NULL, deltas_dev [n_opt] = d price_k / d spot.  One reverse sweep over
+ * the paths serves up to 8 options: the state, vol lookup and step derivative of a
+ * path step are shared, each option carrying its own adjoint, seeded by its own
+ * payoff only, and its own LDS gradient histogram (fewer options per sweep on grids
+ * whose per-option histograms do not fit a block's LDS).  The book's weights are
+ * ignored.  Asynchronous on the context's stream. */
+lv_status lv_per_option_grads_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                                  const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                  int32_t precision, double rate, const void *states_dev, double *grads_dev,
+                                  double *deltas_dev);
 
 /* Test support: Philox words of paths p0 .. p0+n_paths-1 for counter blocks
  * m0 .. m0+n_m-1 into words_dev (device uint32 [n_paths][n_m][4]). */

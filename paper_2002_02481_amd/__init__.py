@@ -81,16 +81,17 @@ SCHEME = {"log_euler": 0, "euler_x": 1}
 def make_opts(precision=32, adjoint="stored", ckpt_every=16, use_graph=False, block=0,
               blocks_per_cu=0, copies=0, window=0, profile=False, autotune=False, fwd_block=0,
               fwd_blocks_per_cu=0, dense_adjoint=False, profile_kinds=0, scheme="log_euler",
-              sigma_bf16=False) -> lv_opts:
+              sigma_bf16=False, rate=0.0) -> lv_opts:
     """scheme: "log_euler" (the Euler step on ln X) or "euler_x" (on X itself).
     sigma_bf16: price the surface with its nodes rounded to bfloat16 (the TPU's storage
-    precision for the interpolation, Sec. IV-D)."""
+    precision for the interpolation, Sec. IV-D).  rate: constant short rate r (the step's
+    trend; prices discounted by e^{-r T})."""
     adj = ADJOINT[adjoint] if isinstance(adjoint, str) else int(adjoint)
     sch = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     return lv_opts(int(precision), adj, int(ckpt_every), int(bool(use_graph)), int(block),
                    int(blocks_per_cu), int(copies), int(window), int(bool(profile)),
                    int(bool(autotune)), int(fwd_block), int(fwd_blocks_per_cu),
-                   int(bool(dense_adjoint)), int(profile_kinds), sch, int(sigma_bf16))
+                   int(bool(dense_adjoint)), int(profile_kinds), sch, int(sigma_bf16), float(rate))
 
 
 def option_order(maturities, n_steps) -> np.ndarray:
@@ -338,25 +339,25 @@ def bump_grad_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed=0, *,
 
 
 def per_option_grads_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed=0, *, spot_axis,
-                         time_axis, is_put=None, precision=32, ctx: Optional[Context] = None):
+                         time_axis, is_put=None, precision=32, rate=0.0, ctx: Optional[Context] = None):
     """Per-option vol-grid gradients from one simulation: the states are stored once by
-    the split forward, then the reverse runs once per option with a one-hot cotangent.
+    the split forward, then one reverse sweep serves up to 8 options at a time, each
+    with its own adjoint (seeded by its own payoff) and its own gradient histogram.
     Returns (prices [n], std_errs [n], grads [n, I, J], deltas [n]) CUDA tensors."""
     import torch
+    ctx = ctx or default_context(sigma.device.index or 0)
     price, stderr, states = forward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed,
                                         spot_axis=spot_axis, time_axis=time_axis, is_put=is_put,
-                                        precision=precision, ctx=ctx)
+                                        precision=precision, rate=rate, ctx=ctx)
     n = price.numel()
     grads = torch.empty((n,) + tuple(sigma.shape), dtype=torch.float64, device=sigma.device)
     deltas = torch.empty(n, dtype=torch.float64, device=sigma.device)
-    for k in range(n):
-        cot = torch.zeros(n, dtype=torch.float64, device=sigma.device)
-        cot[k] = 1.0
-        g, d = backward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, states, cot,
-                            spot_axis=spot_axis, time_axis=time_axis, is_put=is_put,
-                            precision=precision, want_delta=True, ctx=ctx)
-        grads[k] = g
-        deltas[k] = d[0]
+    grid = make_grid(spot_axis, time_axis)
+    book = _Book(strikes, maturities, is_put, None)
+    st = ctx.lib.lv_per_option_grads_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),
+                                         int(n_paths), int(n_steps), int(seed), int(precision), float(rate),
+                                         _ptr(states), _ptr(grads), _ptr(deltas))
+    _check_status(st, ctx.h)
     return price, stderr, grads, deltas
 
 
@@ -367,7 +368,7 @@ def states_bytes(precision: int, n_paths: int, n_steps: int) -> int:
 
 
 def forward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, *, spot_axis, time_axis,
-                is_put=None, precision=32, states=None, ctx: Optional[Context] = None):
+                is_put=None, precision=32, rate=0.0, states=None, ctx: Optional[Context] = None):
     """Split forward: returns (price, std_err, states) CUDA tensors."""
     import torch
     ctx = ctx or default_context(sigma.device.index or 0)
@@ -381,14 +382,14 @@ def forward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, *, spo
     price = torch.empty(book.n, dtype=torch.float64, device=sigma.device)
     stderr = torch.empty_like(price)
     st = ctx.lib.lv_forward_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),
-                                int(n_paths), int(n_steps), int(seed), int(precision), _ptr(states),
-                                _ptr(price), _ptr(stderr))
+                                int(n_paths), int(n_steps), int(seed), int(precision), float(rate),
+                                _ptr(states), _ptr(price), _ptr(stderr))
     _check_status(st, ctx.h)
     return price, stderr, states
 
 
 def backward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, states, cotangent, *,
-                 spot_axis, time_axis, is_put=None, precision=32, want_delta=False,
+                 spot_axis, time_axis, is_put=None, precision=32, rate=0.0, want_delta=False,
                  ctx: Optional[Context] = None):
     """Split backward: gradient [I, J] of sum_k cotangent_k price_k (and delta)."""
     import torch
@@ -400,8 +401,8 @@ def backward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, state
     grad = torch.empty(sigma.shape, dtype=torch.float64, device=sigma.device)
     delta = torch.empty(1, dtype=torch.float64, device=sigma.device) if want_delta else None
     st = ctx.lib.lv_backward_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),
-                                 int(n_paths), int(n_steps), int(seed), int(precision), _ptr(states),
-                                 _ptr(cot), _ptr(grad), _ptr(delta))
+                                 int(n_paths), int(n_steps), int(seed), int(precision), float(rate),
+                                 _ptr(states), _ptr(cot), _ptr(grad), _ptr(delta))
     _check_status(st, ctx.h)
     return grad, delta
 
@@ -412,7 +413,7 @@ def _make_lvprice():
     class LVPrice(torch.autograd.Function):
         """price = LVPrice.apply(sigma, spec) with sigma a CUDA float64 [I, J] tensor and
         spec a dict of spot, strikes, maturities, is_put, n_paths, n_steps, seed,
-        spot_axis, time_axis, precision.  The backward pass is the stored-state adjoint
+        spot_axis, time_axis, precision and (optional) rate.  The backward pass is the stored-state adjoint
         kernel, with grad_output as the per-option cotangent."""
 
         @staticmethod
@@ -422,7 +423,7 @@ def _make_lvprice():
                 sigma, spec["spot"], spec["strikes"], spec["maturities"], spec["n_paths"],
                 spec["n_steps"], spec.get("seed", 0), spot_axis=spec["spot_axis"],
                 time_axis=spec["time_axis"], is_put=spec.get("is_put"),
-                precision=spec.get("precision", 32))
+                precision=spec.get("precision", 32), rate=spec.get("rate", 0.0))
             ctx.save_for_backward(sigma, states)
             ctx.spec = spec
             ctx.mark_non_differentiable(stderr)
@@ -436,7 +437,8 @@ def _make_lvprice():
                 sigma, spec["spot"], spec["strikes"], spec["maturities"], spec["n_paths"],
                 spec["n_steps"], spec.get("seed", 0), states, grad_price,
                 spot_axis=spec["spot_axis"], time_axis=spec["time_axis"],
-                is_put=spec.get("is_put"), precision=spec.get("precision", 32))
+                is_put=spec.get("is_put"), precision=spec.get("precision", 32),
+                rate=spec.get("rate", 0.0))
             return grad, None
 
     return LVPrice

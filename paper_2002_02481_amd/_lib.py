@@ -44,7 +44,7 @@ class lv_opts(C.Structure):
                 ("copies", C.c_int32), ("window", C.c_int32), ("profile", C.c_int32),
                 ("autotune", C.c_int32), ("fwd_block", C.c_int32), ("fwd_blocks_per_cu", C.c_int32),
                 ("dense_adjoint", C.c_int32), ("profile_kinds", C.c_int32), ("scheme", C.c_int32),
-                ("sigma_bf16", C.c_int32)]
+                ("sigma_bf16", C.c_int32), ("rate", C.c_double)]
 
 
 class lv_run_info(C.Structure):
@@ -82,10 +82,12 @@ SIGNATURES = {
     "lv_bump_grad_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _PO, C.c_double,
                                    _i32, _vp]),
     "lv_states_bytes": (C.c_int, [_i32, _i64, _i32, C.POINTER(C.c_size_t)]),
-    "lv_forward_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _i32, _vp,
-                                 _vp, _vp]),
-    "lv_backward_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _i32, _vp,
-                                  _vp, _vp, _vp]),
+    "lv_forward_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _i32, C.c_double,
+                                 _vp, _vp, _vp]),
+    "lv_backward_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _i32, C.c_double,
+                                  _vp, _vp, _vp, _vp]),
+    "lv_per_option_grads_dev": (C.c_int, [_vp, _PG, _vp, C.c_double, _PB, _i64, _i32, _u64, _i32, C.c_double,
+                                          _vp, _vp, _vp]),
     "lv_debug_philox": (C.c_int, [_vp, _u64, _u64, _i32, _u64, _i64, _vp]),
     "lv_debug_normals": (C.c_int, [_vp, _i32, _u64, _u64, _i64, _i32, _vp]),
     "lv_last_run_info": (C.c_int, [_vp, C.POINTER(lv_run_info)]),

@@ -39,7 +39,8 @@ struct Plan {
     uint64_t seed = 0;
     int n_opt = 0, n_taps = 0;
     std::vector<int> tj, cell_lo, tap_step, tap_first, tap_count, opt_put, opt_orig;
-    std::vector<double> ta, opt_strike, weight;
+    std::vector<double> ta, opt_strike, weight, opt_disc;   // opt_disc: e^{-r T_k}, tap order
+    double rate = 0;
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;   // profile: kinds to time (bits)
     int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, bpc = 2, CH = 1;
     int dense = 0;   // reverse kernel sweeps every path (not only those with a nonzero adjoint)
@@ -327,6 +328,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     if (o.scheme != LV_SCHEME_LOG_EULER && o.scheme != LV_SCHEME_EULER_X)
         return fail(ctx, LV_ERR_ARG, "unknown scheme %d", o.scheme);
     if (o.sigma_bf16 != 0 && o.sigma_bf16 != 1) return fail(ctx, LV_ERR_ARG, "sigma_bf16 must be 0 or 1");
+    if (!(std::isfinite(o.rate) && std::fabs(o.rate) <= 1.0)) return fail(ctx, LV_ERR_ARG, "rate must be finite with |r| <= 1");
     if (o.ckpt_every == 0) o.ckpt_every = 16;
     if (o.ckpt_every != 8 && o.ckpt_every != 16 && o.ckpt_every != 32)
         return fail(ctx, LV_ERR_ARG, "ckpt_every must be 8, 16 or 32");
@@ -362,6 +364,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
     pl.dense = o.dense_adjoint ? 1 : 0;
     pl.scheme = o.scheme;
     pl.bf16 = o.sigma_bf16;
+    pl.rate = o.rate;
     pl.G = (int)G;
     pl.Q = 2 * pl.n_opt + 1 + pl.G;
 
@@ -383,6 +386,7 @@ lv_status plan_request(lv_ctx *ctx, const lv_grid *grid, int n_surf, const doubl
         pl.opt_orig.push_back(k);
         pl.opt_put.push_back(book->is_put[k]);
         pl.opt_strike.push_back(book->strike[k]);
+        pl.opt_disc.push_back(std::exp(-pl.rate * book->maturity[k]));
         if (q == 0 || steps[k] != pl.tap_step.back()) {
             pl.tap_step.push_back(steps[k]);
             pl.tap_first.push_back(q);
@@ -461,7 +465,7 @@ int host_fixed_point_bits(const Plan &pl) {
 // Pack the plan's device tables; upload only when they change.
 struct Tables {
     const int *tj, *cell_lo, *tap_step, *tap_first, *tap_count, *opt_put, *opt_orig;
-    const double *ta, *opt_strike, *weight;
+    const double *ta, *opt_strike, *weight, *opt_disc;
 };
 
 template <typename T>
@@ -473,7 +477,7 @@ void put(std::vector<char> &v, const std::vector<T> &x, size_t &off) {
 
 // Byte offsets of the packed tables inside one buffer.
 struct TableOffsets {
-    size_t o[10];
+    size_t o[11];
 };
 
 std::vector<char> pack_tables(const Plan &pl, TableOffsets &to) {
@@ -489,6 +493,7 @@ std::vector<char> pack_tables(const Plan &pl, TableOffsets &to) {
     put(v, pl.ta, o[6]);
     put(v, pl.opt_strike, o[7]);
     put(v, pl.weight, o[8]);
+    put(v, pl.opt_disc, o[10]);
     return v;
 }
 
@@ -506,6 +511,7 @@ Tables tables_at(const void *base, const TableOffsets &to) {
     t.ta = (const double *)(b + o[6]);
     t.opt_strike = (const double *)(b + o[7]);
     t.weight = (const double *)(b + o[8]);
+    t.opt_disc = (const double *)(b + o[10]);
     return t;
 }
 
@@ -567,6 +573,8 @@ lvk::Args make_args(const Space &w, const Plan &pl, const Tables &t, const doubl
     a.opt_strike = t.opt_strike;
     a.opt_orig = t.opt_orig;
     a.cot = t.weight;
+    a.opt_disc = t.opt_disc;
+    a.rate_dt = pl.rate * pl.dt;
     a.Q = pl.Q;
     a.n_tiles = pl.n_tiles;
     a.W = pl.W;
@@ -716,6 +724,8 @@ std::string graph_key(const Plan &pl, const void *ptrs[], int n_ptrs, int n_surf
              pl.blocks, pl.W, pl.WH, pl.K, pl.CH, (pl.dense * 2 + pl.scheme) * 2 + pl.bf16, pl.fblock, pl.fblocks, pl.spot, pl.dt,
              n_surf);
     k += buf;
+    snprintf(buf, sizeof buf, "r%.17g|", pl.rate);
+    k += buf;
     k += adjoint ? "A|" : "F|";
     for (int i = 0; i < n_ptrs; ++i) {
         snprintf(buf, sizeof buf, "%p|", ptrs[i]);
@@ -729,7 +739,7 @@ std::string tune_key(const Plan &pl, bool adjoint) {
     snprintf(buf, sizeof buf, "%d|%d|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", pl.I, pl.J, pl.N,
              pl.axis, pl.P, pl.precision, adjoint ? pl.adjoint : LV_ADJ_NONE, pl.seg, pl.n_opt,
              pl.n_taps, pl.user.block, pl.user.K, pl.user.W, pl.user.bpc, pl.user.fblock,
-             pl.user.fbpc, (int)pl.profile, pl.dense * 2 + pl.scheme);
+             pl.user.fbpc, (int)pl.profile, (pl.dense * 2 + pl.scheme) * 2 + (pl.rate != 0.0));
     return buf;
 }
 
@@ -1128,7 +1138,7 @@ lv_status lv_states_bytes(int32_t precision, int64_t n_paths, int32_t n_steps, s
 
 lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
                          const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
-                         int32_t precision, void *states_dev, double *price_dev,
+                         int32_t precision, double rate, void *states_dev, double *price_dev,
                          double *std_err_dev) {
     if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
     if (!sigma_dev || !states_dev || !price_dev || !std_err_dev)
@@ -1136,6 +1146,7 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
     lv_opts o{};
     o.precision = precision;
     o.adjoint = LV_ADJ_STORED;
+    o.rate = rate;
     Plan pl;
     lv_status s = plan_request(ctx, grid, 1, nullptr, spot, book, n_paths, n_steps, seed, &o, ctx->n_cu,
                                ctx->max_lds, pl);
@@ -1161,14 +1172,15 @@ lv_status lv_forward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_d
 
 lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
                           const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
-                          int32_t precision, const void *states_dev, const double *cotangent_dev,
-                          double *grad_dev, double *delta_dev) {
+                          int32_t precision, double rate, const void *states_dev,
+                          const double *cotangent_dev, double *grad_dev, double *delta_dev) {
     if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
     if (!sigma_dev || !states_dev || !cotangent_dev || !grad_dev)
         return fail(ctx, LV_ERR_ARG, "sigma, states, cotangent and grad are required");
     lv_opts o{};
     o.precision = precision;
     o.adjoint = LV_ADJ_STORED;
+    o.rate = rate;
     Plan pl;
     lv_status s = plan_request(ctx, grid, 1, nullptr, spot, book, n_paths, n_steps, seed, &o, ctx->n_cu,
                                ctx->max_lds, pl);
@@ -1193,6 +1205,66 @@ lv_status lv_backward_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_
     if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     record_info(ctx, pl, true, false, ctx->part.p);
     ctx->info.fixed_point_bits = -1000;   // depends on the device cotangent
+    return LV_OK;
+}
+
+lv_status lv_per_option_grads_dev(lv_ctx *ctx, const lv_grid *grid, const double *sigma_dev, double spot,
+                                  const lv_book *book, int64_t n_paths, int32_t n_steps, uint64_t seed,
+                                  int32_t precision, double rate, const void *states_dev, double *grads_dev,
+                                  double *deltas_dev) {
+    if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    if (!sigma_dev || !states_dev || !grads_dev) return fail(ctx, LV_ERR_ARG, "sigma, states and grads are required");
+    lv_opts o{};
+    o.precision = precision;
+    o.adjoint = LV_ADJ_STORED;
+    o.rate = rate;
+    Plan pl;
+    lv_status s = plan_request(ctx, grid, 1, nullptr, spot, book, n_paths, n_steps, seed, &o, ctx->n_cu,
+                               ctx->max_lds, pl);
+    if (s != LV_OK) return s;
+    // options per sweep: the most (8, 4, 2 or 1) whose grids and histograms fit a block's LDS
+    const int W = 8, block = pl.block;
+    int KO = 8;
+    while (KO > 1 && lvk::lds_bytes_per_option(pl.precision, pl.I, pl.J, block, W, KO) > ctx->max_lds) KO /= 2;
+    if (lvk::lds_bytes_per_option(pl.precision, pl.I, pl.J, block, W, KO) > ctx->max_lds)
+        return fail(ctx, LV_ERR_UNSUPPORTED, "a %d x %d grid per option does not fit a block's LDS", pl.I, pl.J);
+    const int G = pl.G, Q = KO * (1 + G);
+    const long long n_tiles = (pl.P + block - 1) / block;
+    const int blocks = (int)std::min<long long>(n_tiles, ctx->n_cu);
+    HIPCHECK(ctx, hipSetDevice(ctx->device));
+    Tables t;
+    if ((s = upload_tables(ctx, pl, t)) != LV_OK) return s;
+    if ((s = ensure_table(ctx, pl)) != LV_OK) return s;
+    if ((s = ensure(ctx, ctx->part, (size_t)blocks * Q * 8)) != LV_OK) return s;
+    hipStream_t st = ctx->stream();
+    lvk::Args a = make_args(ctx_space(ctx), pl, t, sigma_dev);
+    a.part = (double *)ctx->part.p;
+    a.states = const_cast<void *>(states_dev);
+    a.Q = Q;
+    a.K = 1;
+    a.W = W;
+    a.WH = W;
+    a.n_tiles = (int)n_tiles;
+    hipError_t e = lvk::launch_table(a, pl.precision, st);
+    for (int o0 = 0; o0 < pl.n_opt && e == hipSuccess; o0 += KO) {
+        e = lvk::launch_rev_per_option(a, pl.precision, o0, KO, blocks, block, st);
+        for (int q = 0; q < KO && o0 + q < pl.n_opt && e == hipSuccess; ++q) {
+            const int orig = pl.opt_orig[o0 + q];
+            e = lvk::launch_merge(a.part + (size_t)q * (1 + G), blocks, blocks, Q, 0, G, t.opt_orig, pl.P,
+                                  pl.spot, nullptr, nullptr, grads_dev + (size_t)orig * G,
+                                  deltas_dev ? deltas_dev + orig : nullptr, st);
+        }
+    }
+    if (e != hipSuccess) return fail(ctx, LV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    record_info(ctx, pl, true, false, ctx->part.p);
+    ctx->last_Q = Q;
+    ctx->info.n_blocks = blocks;
+    ctx->info.block = block;
+    ctx->info.tile_paths = block;
+    ctx->info.copies = 1;
+    ctx->info.window = W;
+    ctx->info.hist_window = W;
+    ctx->info.fixed_point_bits = -1000;   // one scale per option
     return LV_OK;
 }
 

@@ -1,8 +1,9 @@
 // lv_internal.h -- interface between the host runtime (lv_api.cpp) and the
-// device kernels (lv_kernels.hip) of the local-vol Monte Carlo library.
+// device kernels (lv_k_*.hip) of the local-vol Monte Carlo library.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -32,7 +33,9 @@ struct Args {
     const int *opt_put;         // [n_opt] tap order
     const double *opt_strike;   // [n_opt] tap order
     const int *opt_orig;        // [n_opt] caller index of each option
+    const double *opt_disc;     // [n_opt] tap order: discount factor e^{-r T_k} (1 at zero rate)
     const double *cot;          // [n_opt] cotangent per option, caller order
+    double rate_dt;             // r dt: the trend each step adds (0: the driftless SDE)
     // storage
     void *states;               // stored planes [N][P]: plane n holds y_{n+1}
     void *ckpt;                 // checkpoint slots [n_seg][n_blocks * block]
@@ -60,8 +63,16 @@ constexpr int adjoint_max_block(int real_bytes) { return real_bytes == 8 ? 512 :
 // LDS bytes a kernel variant needs for the given shape (W table steps, WH
 // histogram steps, CH tiles per live-path list).
 size_t lds_bytes(int variant, int precision, int I, int J, int n_opt, int block, int W, int WH, int K, int CH);
-// Largest fixed-point term the gradient histogram accepts, for the given shape.
-__host__ __device__ double fixed_point_qmax(int precision, int block, int K, long long P);
+// Largest fixed-point term the gradient histogram accepts, for the given shape.  Lanes
+// with a path: at most min(block, P).  FP32: every histogram word receives at most one
+// term per path of its copy class between folds (one tile) and must stay inside int32.
+// FP64: the K words of a node are summed in int64 at the fold, so all of a tile's terms
+// must fit; FP64 is capped at 2^51, where the rounding of terms to integers stays exact.
+__host__ __device__ inline double fixed_point_qmax(int precision, int block, int K, long long P) {
+    const int act = (int)(P < block ? P : block);
+    if (precision == 64) return fmin(ldexp(1.0, 62) / act, ldexp(1.0, 51));
+    return floor(2147483000.0 / (double)((act + K - 1) / K)) - 2.0;
+}
 
 // Optional timing events taken from a launch's own dispatch (start of the first
 // kernel, end of the last), so timing adds no packets between kernels.
@@ -76,6 +87,13 @@ hipError_t launch_fwd(const Args &a, int precision, bool store, int blocks, int 
 hipError_t launch_rev(const Args &a, int precision, int blocks, int block, hipStream_t st, Ev ev = {});
 hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block, hipStream_t st,
                              Ev ev = {});
+// Reverse sweep over stored states giving the options o0 .. o0 + KO - 1 (tap order;
+// KO = 1, 2, 4 or 8) each its own grid and delta: block records [KO][1 + I J] into
+// a.part with a.Q = KO (1 + I J); a.K = 1 and a.W the table window.
+hipError_t launch_rev_per_option(const Args &a, int precision, int o0, int KO, int blocks, int block,
+                                 hipStream_t st);
+// LDS bytes of that sweep for the shape.
+size_t lds_bytes_per_option(int precision, int I, int J, int block, int W, int KO);
 // Fixed-order merge of part [records][Q] into final outputs: payoff entries over
 // the first B_pay records, the rest over the first B_grad.
 hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_opt, int G,
