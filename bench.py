@@ -51,9 +51,16 @@ BYTES_REV = 4.0     # one FP32 state read per live path-step
 METRIC = "path-steps/s for price + full vol-grid adjoint, FP32 vs FP64 GPU at fixed error"
 
 
-def source_sha():
-    src = os.path.join(ROOT, "paper_2002_02481_amd", "csrc", "lv_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+KERNEL_SOURCES = {"fused": "lv_k_fused.hip", "fwd": "lv_k_fwd.hip", "rev": "lv_k_rev.hip", "opt": "lv_k_opt.hip"}
+
+
+def source_sha(kernel: str):
+    """sha256 over the sources a kernel is compiled from: its own file and the shared
+    device header and declarations."""
+    h = hashlib.sha256()
+    for name in (KERNEL_SOURCES[kernel], "lv_device.h", "lv_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2002_02481_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -64,7 +71,7 @@ def measured_traffic(kernel: str, workload: str):
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != source_sha():
+    if rec.get("kernel_source_sha256") != source_sha(kernel):
         return None
     return rec.get("bytes_per_launch")
 

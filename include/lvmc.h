@@ -318,6 +318,20 @@ lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t
                                int32_t n_steps, const lv_opts *opts, int32_t *shapes_out,
                                int32_t max, int32_t *n_out);
 
+/* Launch shapes the autotuner chose, kept across processes.  lv_tuning_save writes
+ * every shape this context has tuned to the text file `path` (overwritten), one line
+ * per request shape, tagged with the device's architecture name and CU count;
+ * *n_out (may be NULL) receives the number of lines.  lv_tuning_load reads such a
+ * file into the context's cache: lines of another architecture or CU count are
+ * skipped, and a request whose key matches a loaded line takes that shape under
+ * lv_opts.autotune (and in the allocation-free entry point) without timing
+ * candidates; *n_out receives the number of lines taken.  A line that is not a
+ * saved tuning, or holds a shape lv_opts would refuse, gives LV_ERR_ARG (lines
+ * before it are kept); so does a file that cannot be opened.  Host only: no GPU
+ * work, the context's stream is not touched. */
+lv_status lv_tuning_save(const lv_ctx *ctx, const char *path, int32_t *n_out);
+lv_status lv_tuning_load(lv_ctx *ctx, const char *path, int32_t *n_out);
+
 lv_status lv_last_run_info(const lv_ctx *ctx, lv_run_info *info);
 
 /* Kernel kinds timed when lv_opts.profile is set. */

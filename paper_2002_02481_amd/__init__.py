@@ -12,6 +12,7 @@ arguments with ctypes and uses PyTorch only for device memory and streams.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -170,6 +171,19 @@ class Context:
 
     def block_grads(self, G: int, n_opt: int = 1) -> np.ndarray:
         return self.block_partials(n_opt, G)["grad"]
+
+    def save_tuning(self, path: str) -> int:
+        """Write the launch shapes this context has tuned to `path`; returns the count."""
+        n = C.c_int32()
+        _check_status(self.lib.lv_tuning_save(self.h, os.fsencode(path), C.byref(n)), self.h)
+        return n.value
+
+    def load_tuning(self, path: str) -> int:
+        """Take the tuned shapes saved in `path` that were timed on this kind of device;
+        returns how many were taken."""
+        n = C.c_int32()
+        _check_status(self.lib.lv_tuning_load(self.h, os.fsencode(path), C.byref(n)), self.h)
+        return n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -67,6 +67,8 @@ _PG, _PB, _PO = C.POINTER(lv_grid), C.POINTER(lv_book), C.POINTER(lv_opts)
 
 SIGNATURES = {
     "lv_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _vp]),
+    "lv_tuning_save": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int32)]),
+    "lv_tuning_load": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int32)]),
     "lv_destroy": (None, [_vp]),
     "lv_set_stream": (C.c_int, [_vp, _vp]),
     "lv_last_error": (C.c_char_p, [_vp]),

@@ -60,6 +60,7 @@ struct lv_ctx {
     hipStream_t own_stream = nullptr;
     int n_cu = 256;
     size_t max_lds = 65536;
+    std::string arch = "unknown";                // gcnArchName of the device (keys saved tunings)
     std::string err = "no error";
     Buf planbuf, part, states, ckpt, sig_stage, out_stage, gtab, bump;
     std::vector<char> plan_bytes;     // what planbuf holds
@@ -886,12 +887,22 @@ lv_status run_dev(lv_ctx *ctx, Plan &pl, int n_surf, const double *sigmas_dev,
     return LV_OK;
 }
 
-int device_cus(int device, size_t *max_lds) {
+int device_cus(int device, size_t *max_lds, std::string *arch = nullptr) {
     hipDeviceProp_t pr;
     if (hipGetDeviceProperties(&pr, device) != hipSuccess) return 256;
     if (max_lds) *max_lds = std::min<size_t>(pr.sharedMemPerBlock, 160 * 1024);
+    if (arch) {
+        // the name up to the first ':' (feature flags such as sramecc+ follow it)
+        std::string a(pr.gcnArchName);
+        *arch = a.substr(0, a.find(':'));
+    }
     return pr.multiProcessorCount;
 }
+
+// Saved tunings: one line per tuned request, "lvmc-tune 1 <arch> <CUs> <key> <block> <K>
+// <W> <bpc> <fblock> <fbpc>" (the key has no blanks).
+constexpr const char *kTuneTag = "lvmc-tune";
+constexpr int kTuneVersion = 1;
 
 }  // namespace
 
@@ -912,7 +923,7 @@ lv_status lv_create(lv_ctx **out, int device, void *hip_stream) {
     lv_ctx *c = new lv_ctx();
     c->device = device;
     c->user_stream = (hipStream_t)hip_stream;
-    c->n_cu = device_cus(device, &c->max_lds);
+    c->n_cu = device_cus(device, &c->max_lds, &c->arch);
     e = hipStreamCreate(&c->own_stream);
     if (e != hipSuccess) {
         delete c;
@@ -1334,6 +1345,60 @@ lv_status lv_tuning_candidates(const lv_grid *grid, const lv_book *book, int64_t
         ++n;
     }
     *n_out = n;
+    return LV_OK;
+}
+
+lv_status lv_tuning_save(const lv_ctx *ctx, const char *path, int32_t *n_out) {
+    if (!ctx || !path) return fail(nullptr, LV_ERR_ARG, "ctx and path are required");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(const_cast<lv_ctx *>(ctx), LV_ERR_ARG, "cannot write %s", path);
+    int n = 0;
+    for (const auto &kv : ctx->tuned) {
+        const Shape &c = kv.second;
+        fprintf(f, "%s %d %s %d %s %d %d %d %d %d %d\n", kTuneTag, kTuneVersion, ctx->arch.c_str(), ctx->n_cu,
+                kv.first.c_str(), c.block, c.K, c.W, c.bpc, c.fblock, c.fbpc);
+        ++n;
+    }
+    const bool ok = fclose(f) == 0;
+    if (!ok) return fail(const_cast<lv_ctx *>(ctx), LV_ERR_ARG, "cannot write %s", path);
+    if (n_out) *n_out = n;
+    return LV_OK;
+}
+
+lv_status lv_tuning_load(lv_ctx *ctx, const char *path, int32_t *n_out) {
+    if (!ctx || !path) return fail(ctx, LV_ERR_ARG, "ctx and path are required");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(ctx, LV_ERR_ARG, "cannot read %s", path);
+    char line[1024];
+    int n = 0, lineno = 0;
+    lv_status st = LV_OK;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '\n' || line[0] == '#') continue;
+        char tag[32], arch[64], key[512];
+        int ver = 0, cus = 0;
+        Shape c;
+        if (sscanf(line, "%31s %d %63s %d %511s %d %d %d %d %d %d", tag, &ver, arch, &cus, key, &c.block, &c.K,
+                   &c.W, &c.bpc, &c.fblock, &c.fbpc) != 11 || strcmp(tag, kTuneTag) != 0) {
+            st = fail(ctx, LV_ERR_ARG, "%s:%d is not a saved tuning", path, lineno);
+            break;
+        }
+        // each field within what lv_opts accepts (the planner checks the LDS fit and the
+        // precision's block limit when the shape is used)
+        auto blk = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+        if (!blk(c.block) || !blk(c.fblock) || c.K < 1 || c.K > 16 || (c.K & (c.K - 1)) || c.W < 8 ||
+            c.W > 64 || c.W % 8 || c.bpc < 1 || c.bpc > 64 || c.fbpc < 1 || c.fbpc > 64) {
+            st = fail(ctx, LV_ERR_ARG, "%s:%d holds an invalid launch shape", path, lineno);
+            break;
+        }
+        // only shapes timed on this kind of device and count of CUs apply here
+        if (ver != kTuneVersion || ctx->arch != arch || cus != ctx->n_cu) continue;
+        ctx->tuned[key] = c;
+        ++n;
+    }
+    fclose(f);
+    if (st != LV_OK) return st;
+    if (n_out) *n_out = n;
     return LV_OK;
 }
 
