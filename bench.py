@@ -86,6 +86,10 @@ def parse():
                     help="headline only: no FP64 pair, other workloads or precision study")
     ap.add_argument("--launch", default="", metavar="BLOCK,COPIES,BPC",
                     help="fix the headline's launch shape instead of autotuning it")
+    ap.add_argument("--only-call-60x30", default="", metavar="BLOCK,COPIES,WINDOW,BPC,FBLOCK,FBPC",
+                    help="only time the 60 x 30 call's stored adjoint at this launch shape (for profiling)")
+    ap.add_argument("--tuning", default="", metavar="FILE",
+                    help="take saved launch shapes from FILE (if it exists) and save the tuned ones to it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -181,7 +185,7 @@ def headline(lv, W, ctx, args):
               ckpt_every=wl.ckpt_every)
 
     def run(out=None, **opts):
-        return lv.price_and_grad_dev(sig, 100.0, b.strike, b.maturity, P, N, wl.seed, out=out, **kw, **opts)
+        return lv.price_and_grad_dev(sig, 100.0, b.strike, b.maturity, P, N, wl.seed, out=out, **{**kw, **opts})
 
     if args.launch:
         bl, k, c = (int(x) for x in args.launch.split(","))
@@ -269,6 +273,56 @@ def headline_fp64(lv, W, ctx, h, args):
                                                      "per_surface": [round(float(x), 6) for x in err]},
         "stderr_price_mean": float(se64.mean()),
     }
+
+
+def headline_stored(lv, ctx, h):
+    """The same 32 surfaces with every state stored (17 GB per surface in FP32) and
+    swept back by the stored reverse kernel instead of checkpoints and recompute."""
+    import numpy as np
+    import torch
+    wl, run = h["wl"], h["run"]
+    o = [t for t in run(adjoint="stored", autotune=True)]
+    torch.cuda.synchronize()
+    ms = best_of(lambda: run(out=o, adjoint="stored", autotune=True), 1, reps=2)
+    S, P, N = len(wl.surfaces), wl.n_paths, wl.n_steps
+    g = o[2].cpu().numpy()
+    gmax = np.abs(h["g32"]).reshape(S, -1).max(axis=1)
+    diff = np.abs(g - h["g32"]).reshape(S, -1).max(axis=1) / gmax
+    info = ctx.run_info()
+    r = {"ms_per_step": ms, "value": S * P * N / (ms * 1e-3),
+         "state_bytes_per_surface": lv.states_bytes(32, P, N),
+         "launch": {k: info[k] for k in ("block", "copies", "window", "blocks_per_cu", "fwd_block",
+                                         "fwd_blocks_per_cu")},
+         "max_bucket_diff_vs_checkpointed_rel_maxg": float(diff.max())}
+    del o
+    torch.cuda.empty_cache()
+    return r
+
+
+def call_60x30_fixed(lv, W, ctx, dev, args):
+    """The 60 x 30 call's stored adjoint at a fixed launch shape, warm-up then timed
+    steps with every kernel's events: the run its rocprofv3 summaries come from."""
+    import torch
+    wl = W.single_call_60x30()
+    s = wl.surface
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device=dev)
+    b, k, w, c, fb, fc = (int(x) for x in args.only_call_60x30.split(","))
+    shape = dict(block=b, copies=k, window=w, blocks_per_cu=c, fwd_block=fb, fwd_blocks_per_cu=fc)
+    run = lambda out=None, **o: lv.price_and_grad_dev(sig, 100.0, wl.book.strike, wl.book.maturity, wl.n_paths,
+                                                      wl.n_steps, wl.seed, spot_axis=s.spot_axis,
+                                                      time_axis=s.time_axis, ctx=ctx, out=out, **shape, **o)
+    out = [t for t in run()]
+    settle(lambda: run(out=out), max(args.warmup, 1))
+    ctx.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run(out=out, profile=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kt = ctx.kernel_times(reset=True)
+    return {"workload": wl.name, "launch": shape, "steps": args.steps, "ms_per_step_with_events": ms,
+            "avg_ms": {k: round(v / n, 5) for k, (v, n) in kt.items() if n}}
 
 
 def call_60x30(lv, W, ctx, dev):
@@ -393,7 +447,42 @@ def book64(lv, W, ctx, dev):
         ms = best_of(f, 20)
         out[name] = {"ms_per_step": ms, "value": wl.n_paths * wl.n_steps / (ms * 1e-3),
                      "graph_replayed": bool(ctx.run_info()["graph_replayed"])}
+    out["per_option_grids"] = per_option_cost(lv, wl, sig, ctx)
     return wl.name, out
+
+
+def per_option_cost(lv, wl, sig, ctx):
+    """Every option's own grid (64 grids) from one stored forward: the reverse sweep
+    that serves up to 8 options at a time, against one reverse pass per option (a
+    one-hot cotangent each) on the same stored states."""
+    import numpy as np
+    import torch
+    s, b = wl.surface, wl.book
+    P, N = wl.n_paths, wl.n_steps
+    kw = dict(spot_axis=s.spot_axis, time_axis=s.time_axis, is_put=b.is_put, ctx=ctx)
+    one_sweep = lambda: lv.per_option_grads_dev(sig, 100.0, b.strike, b.maturity, P, N, wl.seed, **kw)
+    res = one_sweep()
+    settle(one_sweep, 3)
+    ms_sweep = best_of(one_sweep, 5)
+    _, _, states = lv.forward_dev(sig, 100.0, b.strike, b.maturity, P, N, wl.seed, **kw)
+    eye = torch.eye(b.n, dtype=torch.float64, device=sig.device)
+
+    def passes():
+        lv.forward_dev(sig, 100.0, b.strike, b.maturity, P, N, wl.seed, states=states, **kw)
+        return [lv.backward_dev(sig, 100.0, b.strike, b.maturity, P, N, wl.seed, states, eye[k], **kw)[0]
+                for k in range(b.n)]
+
+    g_passes = passes()
+    settle(passes, 2)
+    ms_passes = best_of(passes, 2)
+    g_sweep = res[2].cpu().numpy()
+    diff = max(float(np.abs(g_sweep[k] - g_passes[k].cpu().numpy()).max() / max(np.abs(g_sweep[k]).max(), 1e-300))
+               for k in range(b.n))
+    del states
+    torch.cuda.empty_cache()
+    return {"options": b.n, "ms_forward_and_sweeps_of_up_to_8": ms_sweep,
+            "ms_forward_and_one_pass_per_option": ms_passes, "speedup": ms_passes / ms_sweep,
+            "max_grid_diff_rel_maxg_k": diff}
 
 
 def bs_call_and_vega(spot, strike, sigma, T):
@@ -488,10 +577,15 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = lv.Context(0)
+    if args.only_call_60x30:
+        print(json.dumps(call_60x30_fixed(lv, W, ctx, dev, args)), flush=True)
+        return
+    if args.tuning and os.path.exists(args.tuning):
+        ctx.load_tuning(args.tuning)
     result, h = headline(lv, W, ctx, args)
     if not args.no_variants:
         fp64, acc = headline_fp64(lv, W, ctx, h, args)
-        result["variants"] = {"fp64_gpu": fp64}
+        result["variants"] = {"fp64_gpu": fp64, "fp32_stored_states": headline_stored(lv, ctx, h)}
         acc["fp32_speedup_over_fp64_at_fixed_error"] = fp64["ms_per_step"] / result["ms_per_step"]
         result["accuracy"] = acc
         del h
@@ -504,6 +598,8 @@ def main():
         w[name] = r
         result["workloads"] = w
         result["precision_study"] = precision_study(lv, W, ctx)
+    if args.tuning:
+        ctx.save_tuning(args.tuning)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(result), flush=True)

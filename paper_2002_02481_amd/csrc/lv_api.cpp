@@ -1234,10 +1234,10 @@ lv_status lv_per_option_grads_dev(lv_ctx *ctx, const lv_grid *grid, const double
                                ctx->max_lds, pl);
     if (s != LV_OK) return s;
     // options per sweep: the most (8, 4, 2 or 1) whose grids and histograms fit a block's LDS
-    const int W = 8, block = pl.block;
+    const int block = pl.block;
     int KO = 8;
-    while (KO > 1 && lvk::lds_bytes_per_option(pl.precision, pl.I, pl.J, block, W, KO) > ctx->max_lds) KO /= 2;
-    if (lvk::lds_bytes_per_option(pl.precision, pl.I, pl.J, block, W, KO) > ctx->max_lds)
+    while (KO > 1 && lvk::lds_bytes_per_option(pl.precision, pl.I, pl.J, block, KO) > ctx->max_lds) KO /= 2;
+    if (lvk::lds_bytes_per_option(pl.precision, pl.I, pl.J, block, KO) > ctx->max_lds)
         return fail(ctx, LV_ERR_UNSUPPORTED, "a %d x %d grid per option does not fit a block's LDS", pl.I, pl.J);
     const int G = pl.G, Q = KO * (1 + G);
     const long long n_tiles = (pl.P + block - 1) / block;
@@ -1253,12 +1253,15 @@ lv_status lv_per_option_grads_dev(lv_ctx *ctx, const lv_grid *grid, const double
     a.states = const_cast<void *>(states_dev);
     a.Q = Q;
     a.K = 1;
-    a.W = W;
-    a.WH = W;
     a.n_tiles = (int)n_tiles;
+    // maturity step of every option (tap order): a group's sweep starts at its last one
+    std::vector<int> opt_step(pl.n_opt);
+    for (int t = 0; t < pl.n_taps; ++t)
+        for (int q = 0; q < pl.tap_count[t]; ++q) opt_step[pl.tap_first[t] + q] = pl.tap_step[t];
     hipError_t e = lvk::launch_table(a, pl.precision, st);
     for (int o0 = 0; o0 < pl.n_opt && e == hipSuccess; o0 += KO) {
-        e = lvk::launch_rev_per_option(a, pl.precision, o0, KO, blocks, block, st);
+        const int n_end = opt_step[std::min(o0 + KO, pl.n_opt) - 1];
+        e = lvk::launch_rev_per_option(a, pl.precision, o0, KO, n_end, blocks, block, st);
         for (int q = 0; q < KO && o0 + q < pl.n_opt && e == hipSuccess; ++q) {
             const int orig = pl.opt_orig[o0 + q];
             e = lvk::launch_merge(a.part + (size_t)q * (1 + G), blocks, blocks, Q, 0, G, t.opt_orig, pl.P,
@@ -1273,8 +1276,8 @@ lv_status lv_per_option_grads_dev(lv_ctx *ctx, const lv_grid *grid, const double
     ctx->info.block = block;
     ctx->info.tile_paths = block;
     ctx->info.copies = 1;
-    ctx->info.window = W;
-    ctx->info.hist_window = W;
+    ctx->info.window = 8;
+    ctx->info.hist_window = 8;
     ctx->info.fixed_point_bits = -1000;   // one scale per option
     return LV_OK;
 }

@@ -89,11 +89,12 @@ hipError_t launch_fused_ckpt(const Args &a, int precision, int blocks, int block
                              Ev ev = {});
 // Reverse sweep over stored states giving the options o0 .. o0 + KO - 1 (tap order;
 // KO = 1, 2, 4 or 8) each its own grid and delta: block records [KO][1 + I J] into
-// a.part with a.Q = KO (1 + I J); a.K = 1 and a.W the table window.
-hipError_t launch_rev_per_option(const Args &a, int precision, int o0, int KO, int blocks, int block,
+// a.part with a.Q = KO (1 + I J); a.K = 1.  n_end: the largest maturity step of the
+// group (the sweep starts there).
+hipError_t launch_rev_per_option(const Args &a, int precision, int o0, int KO, int n_end, int blocks, int block,
                                  hipStream_t st);
 // LDS bytes of that sweep for the shape.
-size_t lds_bytes_per_option(int precision, int I, int J, int block, int W, int KO);
+size_t lds_bytes_per_option(int precision, int I, int J, int block, int KO);
 // Fixed-order merge of part [records][Q] into final outputs: payoff entries over
 // the first B_pay records, the rest over the first B_grad.
 hipError_t launch_merge(const double *part, int B_pay, int B_grad, int Q, int n_opt, int G,
