@@ -179,13 +179,14 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 }
             }
 #pragma unroll
-            for (int q4 = SEG / 4 - 1; q4 >= 0; --q4) {
-                // lookups of four steps first (independent of lambda), then the chain
-                Look<R> L[4];
-                R dsd[4];
+            for (int q2 = SEG / 2 - 1; q2 >= 0; --q2) {
+                // lookups of two steps first (independent of lambda), then the chain; pairs
+                // rather than fours keep the 16-step segment within 128 VGPRs (no spills)
+                Look<R> L[2];
+                R dsd[2];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = 4 * q4 + r;
+                for (int r = 0; r < 2; ++r) {
+                    const int k = 2 * q2 + r;
                     if (na + k < N) {
                         L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off, inv_spot,
                                                          amax, spot);
@@ -196,8 +197,8 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     }
                 }
 #pragma unroll
-                for (int r = 3; r >= 0; --r) {
-                    const int k = 4 * q4 + r;
+                for (int r = 1; r >= 0; --r) {
+                    const int k = 2 * q2 + r;
                     const int n = na + k;
                     if (n < N) {
                         if (n + 1 == cur_tap) {
