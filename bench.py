@@ -266,11 +266,22 @@ def headline_fp64(lv, W, ctx, h, args):
     S, P, N = len(wl.surfaces), wl.n_paths, wl.n_steps
     gmax = np.abs(g64).reshape(S, -1).max(axis=1)
     err = np.abs(h["g32"] - g64).reshape(S, -1).max(axis=1) / gmax
+    # Monte Carlo standard error of every bucket of the last surface, from the spread of
+    # the FP64 call's per-block partial sums (blocks take interleaved path tiles)
+    G = g64[-1].size
+    blocks = ctx.block_grads(G)
+    B = blocks.shape[0]
+    se_b = blocks.std(axis=0, ddof=1) * np.sqrt(B) / P
+    d_last = np.abs(h["g32"][-1] - g64[-1]).ravel()
+    ratio = d_last[se_b > 0] / se_b[se_b > 0]
     return {"ms_per_step": ms64, "value": S * P * N / (ms64 * 1e-3), "launch": ctx.run_info()["block"]}, {
         "fp32_vs_fp64_gpu_price_abs_max": float(np.abs(h["p32"] - p64).max()),
         "fp32_price_err_over_stderr_max": float((np.abs(h["p32"] - p64) / se64).max()),
         "fp32_vs_fp64_gpu_max_bucket_err_rel_maxg": {"max": float(err.max()), "median": float(np.median(err)),
                                                      "per_surface": [round(float(x), 6) for x in err]},
+        "fp32_vs_fp64_bucket_err_over_mc_stderr_last_surface": {
+            "max": float(ratio.max()), "q99": float(np.quantile(ratio, 0.99)),
+            "median": float(np.median(ratio)), "blocks": int(B)},
         "stderr_price_mean": float(se64.mean()),
     }
 
