@@ -82,6 +82,27 @@ def test_per_option_grids_fp64(lv, ctx, orc, surface, rate):
     assert abs(float(np.dot(book.weight, deltas)) - d) <= 1e-10 * max(1.0, abs(d))
 
 
+@pytest.mark.parametrize("shape,kind", [((80, 40), "lin"), ((150, 80), "log")])
+def test_per_option_grids_fewer_per_sweep(lv, ctx, orc, shape, kind):
+    """FP64 on grids whose per-option LDS grids allow only 4 (80 x 40) or 1 (150 x 80)
+    options per sweep: every option's grid and delta against the oracle's one-hot
+    gradient, as above (11 options: sweeps of 4, 4, 3, or 11 sweeps of one)."""
+    s = W.tiny_surface(W.LIN if kind == "lin" else W.LOG, shape[0], shape[1], seed=5)
+    book = eleven()
+    P, N = 4099, 52
+    price, grads, deltas = _per_option(lv, ctx, s, book, P, N, 9, 64)
+    refs = _one_hot_refs(orc, s, book, P, N, 9)
+    worst = 0.0
+    for k, r in enumerate(refs):
+        gk = np.abs(r["grad"]).max()
+        err = np.abs(grads[k] - r["grad"]).max() / max(gk, 1e-300)
+        worst = max(worst, err)
+        assert err <= 1e-9, (k, err)
+        assert np.all(grads[k][r["grad"] == 0.0] == 0.0), k
+        assert abs(deltas[k] - r["delta"]) <= 1e-10 * max(1.0, abs(r["delta"])), k
+    F.say(f"  per-option FP64 {shape}: worst max|dg_k|/max|g_k| {worst:.3g}")
+
+
 def test_per_option_grids_fp32(lv, ctx, orc):
     """FP32 on the smooth 21 x 13 surface: every option's grid within 1e-4 max|g_k| of the
     oracle's one-hot gradient (on the FP32-rounded surface), prices within 1e-5 spot."""
