@@ -82,12 +82,17 @@ def test_per_option_grids_fp64(lv, ctx, orc, surface, rate):
     assert abs(float(np.dot(book.weight, deltas)) - d) <= 1e-10 * max(1.0, abs(d))
 
 
-@pytest.mark.parametrize("shape,kind", [((80, 40), "lin"), ((150, 80), "log")])
+@pytest.mark.parametrize("shape,kind", [((80, 40), W.LIN), ((150, 80), W.LOG)])
 def test_per_option_grids_fewer_per_sweep(lv, ctx, orc, shape, kind):
     """FP64 on grids whose per-option LDS grids allow only 4 (80 x 40) or 1 (150 x 80)
     options per sweep: every option's grid and delta against the oracle's one-hot
-    gradient, as above (11 options: sweeps of 4, 4, 3, or 11 sweeps of one)."""
-    s = W.tiny_surface(W.LIN if kind == "lin" else W.LOG, shape[0], shape[1], seed=5)
+    gradient, as above (11 options: sweeps of 4, 4, 3, or 11 sweeps of one).  The
+    surface is the smooth 1-year smile on these axes (a rough random surface on so fine
+    a spot axis makes step derivatives near 2 and adjoints near 1e9, where FP64 rounding
+    alone separates any two summation orders by 1e-5 relative)."""
+    sa = W.Axis(shape[0], kind, 50.0, 200.0)
+    ta = W.Axis(shape[1], W.LIN, 0.0, 1.0)
+    s = W.Surface(sa, ta, W.smile_surface(sa, ta, 0.15, 0.10, decay=True))
     book = eleven()
     P, N = 4099, 52
     price, grads, deltas = _per_option(lv, ctx, s, book, P, N, 9, 64)
