@@ -143,14 +143,14 @@ long long floor_pow2(long long x) {
 // fused kernel.
 int table_window(const Plan &pl, const Shape &sh) { return pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W; }
 
-// Path tiles per live-path list of the reverse kernels: all of a block's tiles, up
-// to 4 (stored states) or 2 (checkpoints: each tile of a list holds its own
-// checkpoint slots and its final states in LDS).
+// Path tiles per live-path list of the stored reverse kernel (all of a block's
+// tiles, up to 4), and checkpoint slot sets in the fused kernel's ring (up to 4: each
+// holds a tile's checkpoints, and its final states in LDS, while paths of that tile
+// wait in the queue).
 int chunk_tiles(const Plan &pl, const Shape &sh, int n_cu) {
     const long long tiles = (pl.P + sh.block - 1) / sh.block;
     const long long blocks = std::min<long long>(tiles, (long long)n_cu * sh.bpc);
-    const long long cap = pl.adjoint == LV_ADJ_CHECKPOINT ? 2 : 4;
-    return (int)std::max<long long>(1, std::min<long long>(cap, (tiles + blocks - 1) / blocks));
+    return (int)std::max<long long>(1, std::min<long long>(4, (tiles + blocks - 1) / blocks));
 }
 
 size_t lds_adj(const Plan &pl, const Shape &sh, int WH, int n_cu) {

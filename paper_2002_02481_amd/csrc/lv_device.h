@@ -190,9 +190,10 @@ __host__ __device__ inline Lds lds_layout(int variant, int rbytes, int accbytes,
     off += align16((size_t)tab_bufs * W * I * 2 * rbytes);
     L.hist = off;
     off += grad ? align16((size_t)WH * K * (I + 1) * accbytes) : 0;   // rows of I + 1 words
-    L.live = off;   // live-path list + wave counts
+    L.live = off;   // live-path list + wave counts (the fused kernel: its queue ring, wave counts
+                    // and the tile of each slot set)
     off += variant == REV_STORED   ? align16(((size_t)CH * wpb * 64 + 16) * 4)
-           : variant == FUSED_CKPT ? align16(((size_t)CH * wpb * 64 + 16) * 4)
+           : variant == FUSED_CKPT ? align16(((size_t)CH * wpb * 64 + 16 + CH) * 4)
                                    : 0;
     L.yfin = off;   // the fused kernel's final state per path of a chunk
     off += variant == FUSED_CKPT ? align16((size_t)CH * wpb * 64 * rbytes) : 0;

@@ -13,13 +13,13 @@ namespace lvk {
 // Checkpoints live in per-block slots reused by every tile of the block.  The
 // LDS table holds one segment; consecutive uses of the same segment (the last
 // one forward then backward, the first one backward then forward for the next
-// tile) share its copy.  The block's tiles b, b + B, ... are taken CH at a time:
-// each is run forward into its own checkpoint slots, then only their live paths (an
+// tile) share its copy.  The block's tiles b, b + B, ... are run forward one at a
+// time, each into the next of CH checkpoint slot sets; only their live paths (an
 // option with a nonzero cotangent in the money at its maturity, as in the stored
-// reverse kernel; every path with a.dense) are swept back, listed in path order and
-// taken in passes of blockDim lanes, so waves beyond the list skip the re-simulation
-// and the sweep.  A lane then reads another lane's checkpoints, which the block
-// barrier makes visible.
+// reverse kernel; every path with a.dense) are swept back, queued in path order
+// across tiles and taken in passes of blockDim lanes, so waves beyond the queue skip
+// the re-simulation and the sweep.  A lane then reads another lane's checkpoints,
+// which the block barrier makes visible.
 // EX: the Euler step on X; the checkpoints hold X, and the
 // re-simulated segment keeps c_n = X_n sqrt(dt) Z_n (the derivative of X_{n+1} in
 // sigma_n) with d X_{n+1} / d X_n = 1 + c_n (sigma_n / X_n + d sigma / d X) (+ r dt
@@ -38,9 +38,16 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     R *tab = (R *)(smem + lay.tab);
     Acc *H = (Acc *)(smem + lay.hist);
     const int CH = a.CH, T = blockDim.x, B = gridDim.x;
-    int *list = (int *)(smem + lay.live);   // live paths of a chunk, as tile-in-chunk * T + lane
-    int *wcnt = list + CH * T;              // per-wave live counts
-    R *yfin = (R *)(smem + lay.yfin);       // state at the last step, per path of the chunk
+    // Live paths wait in a first-in-first-out queue that runs across the block's path
+    // tiles, so that every pass but the last sweeps a full block of them.  A forwarded
+    // tile takes the next of CH checkpoint slot sets (and rows of final states) in a
+    // ring, and only once every path queued from that slot set's previous tile has been
+    // swept; a full ring therefore sends the oldest queued paths through a pass first.
+    const int QCAP = CH * T;
+    int *qent = (int *)(smem + lay.live);   // queue ring [CH T]: slot set * T + lane
+    int *wcnt = qent + QCAP;                // per-wave live counts [16]
+    int *tq_tile = wcnt + 16;               // [CH] the tile a slot set holds
+    R *yfin = (R *)(smem + lay.yfin);       // state at the last step, per slot set and lane
     for (int e = tid; e < G; e += blockDim.x) g64[e] = 0.0;
     for (int e = tid; e < wpb; e += blockDim.x) wlam[e] = 0.0;
     for (int e = tid; e < wpb * a.n_opt * 2; e += blockDim.x) wpart[e] = 0.0;
@@ -61,20 +68,34 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     TabStage<R> stg;
     int tcur = -1;   // segment whose table is in LDS
 
-    for (int c0 = blockIdx.x; c0 < a.n_tiles; c0 += CH * B) {
-      int n_live = 0;
-      for (int kt = 0; kt < CH && c0 + kt * B < a.n_tiles; ++kt) {
-        const int tile = c0 + kt * B;
+    // queue positions (monotone; entry q sits at q mod QCAP), the queue position after
+    // each slot set's tile was listed, tiles forwarded, and the oldest forwarded tile
+    // that still has queued paths: the same in every thread (kept in scalar registers;
+    // CH <= 4, and the slot-set arrays are read and written by unrolled selects)
+    long long q_head = 0, q_tail = 0;
+    long long tq_end[4] = {0, 0, 0, 0};
+    int n_fwd = 0, oldest = 0;
+    auto end_of = [&](int k) {
+        long long v = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v = u == k ? tq_end[u] : v;
+        return v;
+    };
+    int t_next = blockIdx.x;
+    while (t_next < a.n_tiles || q_tail > q_head) {
+      // forward tiles while a slot set is free and the queue holds less than a pass
+      while (t_next < a.n_tiles && n_fwd - oldest < CH && q_tail - q_head < T) {
+        const int ss = n_fwd % CH, tile = t_next;
         const long long p = (long long)tile * T + tid;
         const bool active = p < a.P;
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
-        // ---- forward: checkpoints (slot set kt) and payoff sums
+        // ---- forward: checkpoints (slot set ss) and payoff sums
         R y = EX ? spot : (R)0;
         bool lv = false;
         int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
-            CK[(size_t)(sg * CH + kt) * slot_stride + slot] = y;
+            CK[(size_t)(sg * CH + ss) * slot_stride + slot] = y;
             if (sg != tcur) {
                 __syncthreads();
                 stg.issue(a, na, nw);
@@ -108,33 +129,44 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 }
             }
         }
-        // ---- list the tile's live paths after those of the chunk's earlier tiles
+        // ---- queue the tile's live paths behind those already waiting
         const bool live = active && (a.dense || lv);
         const unsigned long long m = __ballot(live);
         if (lane == 0) wcnt[wave] = __popcll(m);
-        yfin[kt * T + tid] = y;
+        yfin[ss * T + tid] = y;
         __syncthreads();   // also makes every lane's checkpoints visible to the block
-        int woff = n_live, tot = 0;
+        long long woff = q_tail;
+        int tot = 0;
         for (int v = 0; v < wpb; ++v) {
             const int c = wcnt[v];
             woff += v < wave ? c : 0;
             tot += c;
         }
-        if (live) list[woff + __popcll(m & ((1ull << lane) - 1))] = kt * T + tid;
-        n_live += tot;
+        tot = __builtin_amdgcn_readfirstlane(tot);   // the same in every lane and wave
+        if (live) qent[(woff + __popcll(m & ((1ull << lane) - 1))) % QCAP] = ss * T + tid;
+        q_tail += tot;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tq_end[u] = u == ss ? q_tail : tq_end[u];
+        if (tid == 0) tq_tile[ss] = tile;
         __syncthreads();
+        ++n_fwd;
+        t_next += B;
+        while (oldest < n_fwd && end_of(oldest % CH) <= q_head) ++oldest;   // tiles with nothing queued
       }
-      // ---- passes of T listed paths: lane t takes list entry base + t
-      for (int base = 0; base < n_live; base += T) {
-        const bool on = base + tid < n_live;
-        const bool wave_on = base + wave * 64 < n_live;
-        const int e = list[on ? base + tid : base];   // lanes past the list repeat a listed path
+      const int pend = (int)(q_tail - q_head);
+      // ---- one pass over the oldest min(T, pend) queued paths (a full one unless the ring
+      // is full or the tiles have run out): lane t takes entry q_head + t
+      if (pend > 0) {
+        const int cnt = min(T, pend);
+        const bool on = tid < cnt;
+        const bool wave_on = wave * 64 < cnt;
+        const int e = qent[(q_head + (on ? tid : 0)) % QCAP];   // lanes past the queue repeat its head
         const int ek = e / T, src = e - ek * T;
-        const long long ps = (long long)(c0 + ek * B) * T + src;
+        const long long ps = (long long)tq_tile[ek] * T + src;
         const uint32_t slo = (uint32_t)ps, shi = (uint32_t)((unsigned long long)ps >> 32);
         const size_t sslot = (size_t)ek * slot_stride + (size_t)blockIdx.x * T + src;
         // ---- reverse, segment by segment (lam is the adjoint of y times 2^F)
-        R lam = 0, y_next = yfin[e];
+        R lam = 0, y_next = yfin[e];   // e = slot set * T + lane indexes yfin too
         int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
@@ -220,6 +252,8 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         // the adjoint of y_0 = ln(X_0 / spot): with EX, lambda is that of X_0 = spot
         const double l0 = wave_sum(on ? (double)lam * inv_sc * (EX ? a.spot : 1.0) : 0.0);
         if (lane == 0) wlam[wave] += l0;
+        q_head += cnt;
+        while (oldest < n_fwd && end_of(oldest % CH) <= q_head) ++oldest;
       }
     }
     __syncthreads();
