@@ -370,8 +370,8 @@ def test_live_path_sweep_matches_dense(lv, ctx, adjoint, scheme):
 @pytest.mark.parametrize("precision", [32, 64])
 def test_checkpoint_lists_span_tiles(lv, ctx, orc, precision):
     """The checkpointed kernel with 64-lane blocks, one per CU, on 2^15 + 37 paths: 513
-    tiles, more than the blocks, so each block lists the live paths of two tiles at a
-    time (each tile with its own checkpoint slots) and the last, ragged tile alone.
+    tiles, more than the blocks, so each block queues the live paths of two or three
+    tiles (each tile in its own checkpoint slot set) and the last tile is ragged.
     Against the oracle, and bit-equal gradients to sweeping every path."""
     wl = W.small_call()
     P, N = (1 << 15) + 37, wl.n_steps
@@ -386,6 +386,36 @@ def test_checkpoint_lists_span_tiles(lv, ctx, orc, precision):
     assert np.array_equal(got["price"], de["price"])
     assert np.abs(got["grad"] - de["grad"]).max() <= 1e-12 * np.abs(de["grad"]).max()
     assert abs(got["delta"] - de["delta"]) <= 1e-12 * abs(de["delta"])
+
+
+@pytest.mark.parametrize("is_put,strike", [(0, 400.0), (0, 135.0), (0, 100.0), (0, 40.0), (1, 70.0)])
+def test_checkpoint_queue_live_fractions(lv, ctx, orc, is_put, strike):
+    """The fused kernel's live-path queue at live fractions from none to all: 64-lane
+    blocks, one per CU, 2^16 + 5 paths (1025 tiles, 4 or 5 per block, a ring of 4
+    checkpoint slot sets).  No live path (a call struck at 400): every tile leaves the
+    ring at once; a few (135, the put at 70): the ring fills before a pass does and
+    forces partial passes; about half (100); all (40): a full pass per tile.  FP64
+    against the oracle at the tight bar, and equal to sweeping every path."""
+    s = W.small_surface()
+    book = W.Book([is_put], [strike], [1.0], [1.0])
+    P, N = (1 << 16) + 5, 52
+    ref = orc.price_and_grad(s, book, P, N, seed=2)
+    shape = dict(adjoint="checkpoint", block=64, blocks_per_cu=1, precision=64)
+    got = gpu_run(lv, ctx, s, book, P, N, 2, **shape)
+    info = ctx.run_info()
+    assert info["block"] == 64 and info["n_blocks"] <= 256, info
+    nz = float(np.mean(ref["grad"] != 0.0))
+    say(f"  queue, {'put' if is_put else 'call'} K={strike}: nonzero buckets {nz:.2f}")
+    if np.any(ref["grad"]):
+        assert_parity(got, ref, 64, f"checkpoint queue K={strike}")
+    else:
+        assert np.all(got["grad"] == 0.0) and got["delta"] == 0.0
+        assert np.allclose(got["price"], ref["price"], rtol=1e-11, atol=1e-300)
+    de = gpu_run(lv, ctx, s, book, P, N, 2, dense_adjoint=True, **shape)
+    assert np.array_equal(got["price"], de["price"])
+    gm = max(np.abs(de["grad"]).max(), 1e-300)
+    assert np.abs(got["grad"] - de["grad"]).max() <= 1e-12 * gm
+    assert abs(got["delta"] - de["delta"]) <= 1e-12 * max(abs(de["delta"]), 1e-300)
 
 
 def test_block_shapes_agree(lv, ctx, orc):
