@@ -36,15 +36,19 @@ PEAK_SLOTS_T = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_FP32_TFLOPS = 157.3
 
 # Algorithmic work in VALU issue slots: each operation of the method weighted by its
-# issue cost on gfx950 (full rate 1; 32x32->64 multiply 2.4; transcendental 3.1).
+# issue cost on gfx950 (full rate 1; 32x32->64 multiply 2.4; transcendental 3.1).  A
+# Philox round is two multiplies and two three-input XORs (one instruction each on
+# gfx950); a uniform is a funnel shift and a subtraction; the lookup's cell fraction is
+# one instruction.
 # Log-spot axis, per path-step:
-SLOTS_FWD = 37.7    # Philox/4 17 + uniforms 3 + Box-Muller 7.7 + lookup 7 + Euler 2 + store 1
-SLOTS_REV = 26.1    # per live path-step: load 1 + lookup 7 + slope 4 + c_n 6.1 + adjoint 2 + scatter 6
+SLOTS_FWD = 35.7    # Philox/4 17 + uniforms 2 + Box-Muller 7.7 + lookup 6 + Euler 2 + store 1
+SLOTS_REV = 25.1    # per live path-step: load 1 + lookup 6 + slope 4 + c_n 6.1 + adjoint 2 + scatter 6
 # Linear spot axis, checkpointed (fused) kernel: the spot S = S0 exp(y) for the lookup
-# costs 5.1 (two multiplies and an exp) wherever a lookup is made.
-SLOTS_FUSED_ALL = 41.9    # every path-step: forward 37.7 - store 1 + exp 5.1 + checkpoint 1/16
-SLOTS_FUSED_LIVE = 65.9   # every live path-step: re-simulation 41.9 - 1/16 + c_n 1, and the
-                          # reverse: lookup 7 + exp 5.1 + slope 3 + adjoint 2 + scatter 6
+# costs 5.1 (two multiplies and an exp) wherever a forward lookup is made.
+SLOTS_FUSED_ALL = 39.9    # every path-step: forward 35.7 - store 1 + exp 5.1 + checkpoint 1/16
+SLOTS_FUSED_LIVE = 57.8   # every live path-step: re-simulation 39.9 - 1/16 + c_n 1, and the
+                          # reverse: lookup 6 + slope 3 + adjoint 2 + scatter 6 (the segment
+                          # keeps the re-simulation's spots, so no exp)
 BYTES_FWD = 4.0     # one FP32 state written per path-step
 BYTES_REV = 4.0     # one FP32 state read per live path-step
 

@@ -51,14 +51,20 @@ struct Words {
     uint32_t x, y, z, w;
 };
 
+// a ^ b ^ c in one instruction: gfx950's three-input bit operation with the truth
+// table 0x96 (the parity of the three input bits); the compiler emits two XORs for it.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(b >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(a >> 32), c3, k1);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;
@@ -80,8 +86,11 @@ template <>
 struct Math<float> {
     typedef int Acc;                       // fixed-point histogram word
     static constexpr int FMAX = 40;
+    // (2k + 1) 2^-24 with k = w >> 9: the float with exponent 0 and mantissa k (the funnel
+    // shift of 0x7f above w puts k under a biased exponent of 127) is 1 + k 2^-23, and
+    // subtracting 1 - 2^-24 is exact (the result is a multiple of 2^-24 below 1)
     __device__ static __forceinline__ float uniform(uint32_t w) {
-        return fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+        return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, w, 9)) - 0x1.fffffep-1f;
     }
     // sqrt(dt) * (Z_a, Z_b) from one word pair (Box-Muller); the hardware sine
     // and cosine take their argument in revolutions, i.e. compute sin(2 pi u).
@@ -284,7 +293,9 @@ __device__ __forceinline__ Look<R> lookup_at(R x, const R *trow, R inv_du, R a_o
     // below the range ac = 0.  So "strictly inside" is ac > 0 (the top needs no test).
     L.in = ac > (R)0;
     L.i = (int)ac;
-    L.f = ac - (R)L.i;
+    // ac >= 0: the fraction ac - floor(ac) is exact, and in single precision one instruction
+    if constexpr (sizeof(R) == 4) L.f = __builtin_amdgcn_fractf(ac);
+    else L.f = ac - (R)L.i;
     const R c = trow[2 * L.i], d = trow[2 * L.i + 1];
     L.s = fma(L.f, d, c);
     L.d = d;
@@ -349,9 +360,9 @@ __device__ __forceinline__ void fwd_payoffs(const Args &a, int tap, R y, bool ac
 // Adjoint seeds at step n+1: lambda += scale sum_k w_k d payoff_k / d state (the
 // adjoint kernels carry lambda scaled by the fixed-point scale 2^F); the state is y
 // (d payoff / d y = +-S in the money) or, with EX, X (d payoff / d X = +-1).
+// rev_seeds_at takes the spot S = spot e^y of the state (with EX, X itself).
 template <typename R, bool EX>
-__device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam, double scale) {
-    const R S = EX ? y : (R)a.spot * Math<R>::ex(y);
+__device__ __forceinline__ R rev_seeds_at(const Args &a, int tap, R S, R lam, double scale) {
     const R D = EX ? (R)1 : S;
     const double Sd = (double)S;
     const int k0 = ldu(a.tap_first + tap), kc = ldu(a.tap_count + tap);
@@ -366,6 +377,11 @@ __device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam, doubl
         }
     }
     return lam;
+}
+
+template <typename R, bool EX>
+__device__ __forceinline__ R rev_seeds(const Args &a, int tap, R y, R lam, double scale) {
+    return rev_seeds_at<R, EX>(a, tap, EX ? y : (R)a.spot * Math<R>::ex(y), lam, scale);
 }
 
 // Fold of the histogram rows of steps [h0, h0 + nh) into the block's FP64 grid.
@@ -413,19 +429,25 @@ __device__ void fold(const Args &a, typename Math<R>::Acc *H, double *g64, int h
 }
 
 // Scatter of one step's adjoint term x (lambda c, already scaled by 2^F): x(1-f)
-// to node i and x f to node i+1 of this lane's histogram row hrow.
-template <typename R>
+// to node i and x f to node i+1 of this lane's histogram row hrow.  SKIP0: lanes
+// whose term is zero stay idle (for sweeps where many lanes carry a zero adjoint);
+// otherwise every lane adds, a zero where its term is zero or out of range, so the
+// common case takes no branch.
+template <typename R, bool SKIP0 = true>
 __device__ __forceinline__ void scatter(const Args &a, typename Math<R>::Acc *hrow, double *g64, int n,
                                         const Look<R> &L, R x, R qm, bool magic, double inv_sc) {
     typedef typename Math<R>::Acc Acc;
-    if (x == (R)0) return;   // lanes whose adjoint is zero (paths out of the money) stay idle
-    if (fabs(x) <= qm) {
+    if (SKIP0 && x == (R)0) return;
+    const bool in_range = fabs(x) <= qm;   // false for a term that is not finite
+    if (SKIP0 ? in_range : true) {
+        const R xq = SKIP0 || in_range ? x : (R)0;
         Acc q0, q1;
-        Math<R>::to_acc2(x, x * L.f, magic, q0, q1);
+        Math<R>::to_acc2(xq, xq * L.f, magic, q0, q1);
         Acc *h = hrow + L.i;
         Math<R>::acc_add(h, q0);
         Math<R>::acc_add(h + 1, q1);
-    } else {
+    }
+    if (!in_range) {
         // rare: outside the fixed-point range (or not finite): FP64 LDS atomics
         // straight into the block's grid (no fold runs while steps scatter)
         const int i = min(L.i, a.I - 2);

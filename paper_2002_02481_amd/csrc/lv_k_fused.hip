@@ -8,8 +8,9 @@ namespace lvk {
 // Fused kernel with checkpoints: per path tile, a forward pass that keeps the
 // state at the start of every SEG-step segment and the payoff sums, then the
 // reverse pass segment by segment (last first): the segment is re-simulated
-// from its checkpoint with the same Philox counters, its states and
-// c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and swept backwards.
+// from its checkpoint with the same Philox counters, its states (on a linear spot
+// axis their spots) and c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and
+// swept backwards.
 // Checkpoints live in per-block slots reused by every tile of the block.  The
 // LDS table holds one segment; consecutive uses of the same segment (the last
 // one forward then backward, the first one backward then forward for the next
@@ -29,7 +30,10 @@ template <typename R, int AXIS, int SEG, bool MAGIC, bool EX, bool RT>
 __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) {
     typedef typename Math<R>::Acc Acc;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wpb = blockDim.x >> 6, tid = threadIdx.x, lane = tid & 63;
+    // the wave index is the same in every lane of a wave; saying so keeps the branches
+    // on it (a wave with no queued path skips the sweep) and all that follows them uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int I = a.I, J = a.J, N = a.N, G = I * J, WH = a.WH;
     const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, WH, a.K, a.CH);
     double *g64 = (double *)(smem + lay.g64);
@@ -165,8 +169,13 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         const long long ps = (long long)tq_tile[ek] * T + src;
         const uint32_t slo = (uint32_t)ps, shi = (uint32_t)((unsigned long long)ps >> 32);
         const size_t sslot = (size_t)ek * slot_stride + (size_t)blockIdx.x * T + src;
-        // ---- reverse, segment by segment (lam is the adjoint of y times 2^F)
+        // ---- reverse, segment by segment (lam is the adjoint of y times 2^F).  On a
+        // linear spot axis with log-Euler steps the segment keeps the spots S_n = spot e^{y_n}
+        // the re-simulation computed for its lookups, not y_n: the sweep's lookups and
+        // seeds need only S_n (the same values, so no exp in the sweep).
+        constexpr bool HS = AXIS == 0 && !EX;
         R lam = 0, y_next = yfin[e];   // e = slot set * T + lane indexes yfin too
+        if (HS) y_next = spot * Math<R>::ex(y_next);
         int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
@@ -184,7 +193,8 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 tcur = sg;
             }
             if (!wave_on) continue;   // no live path in this wave (the barriers above are the block's)
-            const int hb = na - hcur * WH;   // histogram row of the segment's first step
+            // this lane's histogram row of the segment's first step
+            Acc *const hseg = Hl + (na - hcur * WH) * KI1;
             R ys[SEG], cs[SEG];
             R yy = CK[(size_t)sg * CH * slot_stride + sslot];
 #pragma unroll
@@ -201,7 +211,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         if (n0 + r < N) {
                             const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
                                                                         inv_spot, amax, spot);
-                            ys[k] = yy;
+                            ys[k] = HS ? L.S : yy;
                             // the forward's own arithmetic, so the re-simulated states (and
                             // with them the seed tests) are the forward's bit for bit
                             cs[k] = EX ? yy * z[r] : fma((R)-2 * hdt, L.s, z[r]);
@@ -220,8 +230,13 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 for (int r = 0; r < 2; ++r) {
                     const int k = 2 * q2 + r;
                     if (na + k < N) {
-                        L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off, inv_spot,
-                                                         amax, spot);
+                        if (HS) {
+                            L[r] = lookup_at<R>(ys[k], tab + 2 * k * I, inv_du, a_off, amax);
+                            L[r].S = ys[k];
+                        } else {
+                            L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off,
+                                                             inv_spot, amax, spot);
+                        }
                         R d = L[r].in ? L[r].d * inv_du : (R)0;
                         if (AXIS == 0) d *= L[r].S;
                         // EX: sigma / X + d sigma / d X (on a log axis d sigma / d X = (d / du) / X)
@@ -234,14 +249,15 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     const int n = na + k;
                     if (n < N) {
                         if (n + 1 == cur_tap) {
-                            lam = rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
+                            lam = HS ? rev_seeds_at<R, EX>(a, rtap, y_next, lam, scd)
+                                     : rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
                             if (!on) lam = 0;
                             --rtap;
                             cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
                         }
                         const R x = lam * cs[k];   // lam carries 2^F: x is the fixed-point term
                         lam = fma(x, dsd[r], (EX && RT) ? fma(lam, rdt, lam) : lam);
-                        scatter<R>(a, Hl + (hb + k) * KI1, g64, n, L[r], x, qm, magic, inv_sc);
+                        scatter<R, false>(a, hseg + k * KI1, g64, n, L[r], x, qm, magic, inv_sc);
                         y_next = ys[k];
                     }
                 }
