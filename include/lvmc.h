@@ -151,7 +151,13 @@ enum { LV_SCHEME_LOG_EULER = 0, LV_SCHEME_EULER_X = 1 };
 
 /* Create a context on HIP device `device` that launches on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  The context owns a device
- * workspace that grows on demand and is freed by lv_destroy. */
+ * workspace that grows on demand and is freed by lv_destroy.  If the environment
+ * variable LVMC_TUNING_FILE names a file, lv_create loads the saved tunings in it
+ * (as lv_tuning_load; a file that is not a tuning file fails lv_create with
+ * LV_ERR_ARG), and every shape the autotuner then chooses is written back to it: its
+ * lines for other devices or other request shapes are kept, this context's shapes
+ * replace or follow them, and the file is replaced by renaming a temporary file
+ * written beside it (a failure to write fails the autotuned call with LV_ERR_ARG). */
 lv_status lv_create(lv_ctx **out, int device, void *hip_stream);
 void lv_destroy(lv_ctx *ctx);
 lv_status lv_set_stream(lv_ctx *ctx, void *hip_stream);

@@ -7,10 +7,13 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "lv_internal.h"
 #include "lvmc.h"
@@ -70,6 +73,7 @@ struct lv_ctx {
     void *scratch = nullptr;                     // this device's allocation-free workspace
     std::vector<char> scratch_tables;            // host copy of the tables it last uploaded
     std::map<std::string, Shape> tuned;          // autotuner results per request shape
+    std::string tune_path;                       // LVMC_TUNING_FILE at creation ("" = none)
     bool last_autotuned = false;
     // kernel timing (lv_opts.profile)
     struct Timed {
@@ -782,6 +786,48 @@ bool user_allows(const Plan &pl, const Shape &c) {
              (pl.user.fblock && c.fblock != pl.user.fblock) || (pl.user.fbpc && c.fbpc != pl.user.fbpc));
 }
 
+// Saved tunings: one line per tuned request, "lvmc-tune 1 <arch> <CUs> <key> <block> <K>
+// <W> <bpc> <fblock> <fbpc>" (the key has no blanks).
+constexpr const char *kTuneTag = "lvmc-tune";
+constexpr int kTuneVersion = 1;
+
+void write_tuning_line(FILE *f, const lv_ctx *ctx, const std::string &key, const Shape &c) {
+    fprintf(f, "%s %d %s %d %s %d %d %d %d %d %d\n", kTuneTag, kTuneVersion, ctx->arch.c_str(), ctx->n_cu,
+            key.c_str(), c.block, c.K, c.W, c.bpc, c.fblock, c.fbpc);
+}
+
+// The tuning file named by LVMC_TUNING_FILE after the autotuner added a shape: the
+// lines already there for other devices, or for request shapes this context has not
+// tuned (another process may have added them since this one read the file), are kept
+// as they are; this context's shapes follow.  Written to a temporary file in the same
+// folder and renamed over the old one, so readers see the old file or the new one.
+lv_status save_tunings_merged(lv_ctx *ctx, const char *path) {
+    std::vector<std::string> keep;
+    if (FILE *f = fopen(path, "r")) {
+        char line[1024];
+        while (fgets(line, sizeof line, f)) {
+            char tag[32], arch[64], key[512];
+            int ver = 0, cus = 0;
+            const bool ours = sscanf(line, "%31s %d %63s %d %511s", tag, &ver, arch, &cus, key) == 5 &&
+                              strcmp(tag, kTuneTag) == 0 && ver == kTuneVersion && ctx->arch == arch &&
+                              cus == ctx->n_cu && ctx->tuned.count(key);
+            if (!ours && line[0] != '\n') keep.push_back(line);
+        }
+        fclose(f);
+    }
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(ctx, LV_ERR_ARG, "cannot write the tuning file %s (LVMC_TUNING_FILE)", tmp.c_str());
+    for (const std::string &l : keep) fputs(l.c_str(), f);
+    for (const auto &kv : ctx->tuned) write_tuning_line(f, ctx, kv.first, kv.second);
+    const bool ok = fclose(f) == 0 && rename(tmp.c_str(), path) == 0;
+    if (!ok) {
+        (void)remove(tmp.c_str());
+        return fail(ctx, LV_ERR_ARG, "cannot write the tuning file %s (LVMC_TUNING_FILE)", path);
+    }
+    return LV_OK;
+}
+
 // Autotuner: the separate forward kernel's shape first (stored and price-only
 // paths), then the adjoint (or fused) kernel's shape with that forward; each
 // candidate is timed on the first surface in two sweeps over the candidates (the
@@ -823,6 +869,7 @@ lv_status autotune(lv_ctx *ctx, Plan &pl, const double *sigmas_dev, bool adjoint
         (void)hipEventDestroy(e1);
         if (st != LV_OK) return st;
         it = ctx->tuned.emplace(key, best).first;
+        if (!ctx->tune_path.empty() && (st = save_tunings_merged(ctx, ctx->tune_path.c_str())) != LV_OK) return st;
     }
     return apply_shape(ctx, pl, it->second, ctx->n_cu, ctx->max_lds, false, false);
 }
@@ -899,11 +946,6 @@ int device_cus(int device, size_t *max_lds, std::string *arch = nullptr) {
     return pr.multiProcessorCount;
 }
 
-// Saved tunings: one line per tuned request, "lvmc-tune 1 <arch> <CUs> <key> <block> <K>
-// <W> <bpc> <fblock> <fbpc>" (the key has no blanks).
-constexpr const char *kTuneTag = "lvmc-tune";
-constexpr int kTuneVersion = 1;
-
 }  // namespace
 
 // ===========================================================================
@@ -935,6 +977,19 @@ lv_status lv_create(lv_ctx **out, int device, void *hip_stream) {
         (void)hipStreamDestroy(c->own_stream);
         delete c;
         return fail(nullptr, LV_ERR_HIP, "workspace address on device %d: %s", device, hipGetErrorString(e));
+    }
+    // shapes tuned by earlier processes, if LVMC_TUNING_FILE names a file that exists
+    const char *tp = getenv("LVMC_TUNING_FILE");
+    if (tp && *tp) {
+        c->tune_path = tp;
+        if (FILE *f = fopen(tp, "r")) {
+            fclose(f);
+            if (lv_tuning_load(c, tp, nullptr) != LV_OK) {
+                const std::string msg = c->err;
+                lv_destroy(c);
+                return fail(nullptr, LV_ERR_ARG, "LVMC_TUNING_FILE: %s", msg.c_str());
+            }
+        }
     }
     *out = c;
     return LV_OK;
@@ -1357,9 +1412,7 @@ lv_status lv_tuning_save(const lv_ctx *ctx, const char *path, int32_t *n_out) {
     if (!f) return fail(const_cast<lv_ctx *>(ctx), LV_ERR_ARG, "cannot write %s", path);
     int n = 0;
     for (const auto &kv : ctx->tuned) {
-        const Shape &c = kv.second;
-        fprintf(f, "%s %d %s %d %s %d %d %d %d %d %d\n", kTuneTag, kTuneVersion, ctx->arch.c_str(), ctx->n_cu,
-                kv.first.c_str(), c.block, c.K, c.W, c.bpc, c.fblock, c.fbpc);
+        write_tuning_line(f, ctx, kv.first, kv.second);
         ++n;
     }
     const bool ok = fclose(f) == 0;

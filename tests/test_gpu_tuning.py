@@ -78,3 +78,30 @@ def test_malformed_files_are_refused(lv, tmp_path, text):
 def test_missing_file_is_refused(lv, tmp_path):
     with pytest.raises(lv.LVError):
         lv.Context(0).load_tuning(str(tmp_path / "absent.txt"))
+
+
+def test_tuning_file_named_by_the_environment(lv, tmp_path, monkeypatch):
+    """LVMC_TUNING_FILE: a context created with it set writes what its autotuner chose
+    there, keeping the lines of other devices; a later context loads the file at
+    creation and takes the same shape; a file that is not a tuning file fails creation."""
+    path = tmp_path / "tune_env.txt"
+    foreign = "lvmc-tune 1 gfx000 7 some-other-request 512 2 16 1 512 2\n"
+    path.write_text(foreign)
+    monkeypatch.setenv("LVMC_TUNING_FILE", str(path))
+    a = lv.Context(0)
+    res_a, shape_a = _call(lv, a, adjoint="stored", autotune=True)
+    lines = path.read_text().splitlines()
+    assert lines[0] == foreign.strip()                      # another device's line kept
+    assert len(lines) == 2 and lines[1].startswith("lvmc-tune 1 gfx")
+    b = lv.Context(0)                                       # loads the file when created
+    saved = str(tmp_path / "b.txt")
+    assert b.save_tuning(saved) == 1 and open(saved).read().strip() == lines[1]
+    res_b, shape_b = _call(lv, b, adjoint="stored", autotune=True)
+    assert shape_b == shape_a
+    for x, y in zip(res_a, res_b):
+        assert np.array_equal(x, y)
+    assert path.read_text().splitlines() == lines           # nothing new was tuned
+    path.write_text("not a tuning\n")
+    with pytest.raises(lv.LVError) as ei:
+        lv.Context(0)
+    assert ei.value.status == lv._lib.LV_ERR_ARG and "LVMC_TUNING_FILE" in str(ei.value)
