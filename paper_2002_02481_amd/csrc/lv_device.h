@@ -276,6 +276,7 @@ struct Look {
     R f;       // position inside the spot cell
     R d;       // node difference of the cell (d sigma / d a)
     R S;       // spot (linear axis only)
+    R E;       // S / spot = e^y (linear axis, log-Euler state only)
     int i;     // lower spot node
     bool in;   // strictly inside the spot range (slope is zero outside)
 };
@@ -302,13 +303,16 @@ __device__ __forceinline__ Look<R> lookup_at(R x, const R *trow, R inv_du, R a_o
     return L;
 }
 
-// Lookup at log-spot state y = ln(S / spot) (L.S = S on a linear axis).
+// Lookup at log-spot state y = ln(S / spot) (L.S = S on a linear axis).  On a linear
+// axis the coordinate is E / du' + a_off with E = e^y and du' = du / spot, so a lookup
+// that does not need S itself takes no multiply for it.
 template <typename R, int AXIS>
 __device__ __forceinline__ Look<R> lookup(R y, const R *trow, R inv_du, R a_off, R amax, R spot) {
     if (AXIS == 0) {
-        const R S = spot * Math<R>::ex(y);
-        Look<R> L = lookup_at<R>(S, trow, inv_du, a_off, amax);
-        L.S = S;
+        const R E = Math<R>::ex(y);
+        Look<R> L = lookup_at<R>(E, trow, spot * inv_du, a_off, amax);
+        L.S = spot * E;
+        L.E = E;
         return L;
     }
     return lookup_at<R>(y, trow, inv_du, a_off, amax);

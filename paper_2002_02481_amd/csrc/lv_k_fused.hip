@@ -9,7 +9,7 @@ namespace lvk {
 // state at the start of every SEG-step segment and the payoff sums, then the
 // reverse pass segment by segment (last first): the segment is re-simulated
 // from its checkpoint with the same Philox counters, its states (on a linear spot
-// axis their spots) and c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and
+// axis e^y = S / spot) and c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and
 // swept backwards.
 // Checkpoints live in per-block slots reused by every tile of the block.  The
 // LDS table holds one segment; consecutive uses of the same segment (the last
@@ -170,12 +170,13 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         const uint32_t slo = (uint32_t)ps, shi = (uint32_t)((unsigned long long)ps >> 32);
         const size_t sslot = (size_t)ek * slot_stride + (size_t)blockIdx.x * T + src;
         // ---- reverse, segment by segment (lam is the adjoint of y times 2^F).  On a
-        // linear spot axis with log-Euler steps the segment keeps the spots S_n = spot e^{y_n}
-        // the re-simulation computed for its lookups, not y_n: the sweep's lookups and
-        // seeds need only S_n (the same values, so no exp in the sweep).
+        // linear spot axis with log-Euler steps the segment keeps E_n = e^{y_n} = S_n / spot,
+        // which the re-simulation computed for its lookups, not y_n: the sweep's lookups,
+        // slopes and seeds need only E_n (the same values, so no exp in the sweep).
         constexpr bool HS = AXIS == 0 && !EX;
+        const R s_inv_du = spot * inv_du;   // the lookups' 1 / du' (du' = du / spot)
         R lam = 0, y_next = yfin[e];   // e = slot set * T + lane indexes yfin too
-        if (HS) y_next = spot * Math<R>::ex(y_next);
+        if (HS) y_next = Math<R>::ex(y_next);
         int rtap = a.n_taps - 1, cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
         int hcur = ((n_seg - 1) * SEG) / WH;
         for (int sg = n_seg - 1; sg >= 0; --sg) {
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         if (n0 + r < N) {
                             const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
                                                                         inv_spot, amax, spot);
-                            ys[k] = HS ? L.S : yy;
+                            ys[k] = HS ? L.E : yy;
                             // the forward's own arithmetic, so the re-simulated states (and
                             // with them the seed tests) are the forward's bit for bit
                             cs[k] = EX ? yy * z[r] : fma((R)-2 * hdt, L.s, z[r]);
@@ -231,16 +232,17 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     const int k = 2 * q2 + r;
                     if (na + k < N) {
                         if (HS) {
-                            L[r] = lookup_at<R>(ys[k], tab + 2 * k * I, inv_du, a_off, amax);
-                            L[r].S = ys[k];
+                            // d sigma / d y = (d / du) S = (d / du') E
+                            L[r] = lookup_at<R>(ys[k], tab + 2 * k * I, s_inv_du, a_off, amax);
+                            dsd[r] = L[r].in ? L[r].d * s_inv_du * ys[k] : (R)0;
                         } else {
                             L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off,
                                                              inv_spot, amax, spot);
+                            R d = L[r].in ? L[r].d * inv_du : (R)0;
+                            if (AXIS == 0) d *= L[r].S;
+                            // EX: sigma / X + d sigma / d X (on a log axis d sigma / d X = (d / du) / X)
+                            dsd[r] = EX ? (L[r].s + d) * Math<R>::rcp(ys[k]) : d;
                         }
-                        R d = L[r].in ? L[r].d * inv_du : (R)0;
-                        if (AXIS == 0) d *= L[r].S;
-                        // EX: sigma / X + d sigma / d X (on a log axis d sigma / d X = (d / du) / X)
-                        dsd[r] = EX ? (L[r].s + d) * Math<R>::rcp(ys[k]) : d;
                     }
                 }
 #pragma unroll
@@ -249,7 +251,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     const int n = na + k;
                     if (n < N) {
                         if (n + 1 == cur_tap) {
-                            lam = HS ? rev_seeds_at<R, EX>(a, rtap, y_next, lam, scd)
+                            lam = HS ? rev_seeds_at<R, EX>(a, rtap, spot * y_next, lam, scd)
                                      : rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
                             if (!on) lam = 0;
                             --rtap;
