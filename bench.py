@@ -43,12 +43,12 @@ PEAK_FP32_TFLOPS = 157.3
 # Log-spot axis, per path-step:
 SLOTS_FWD = 35.7    # Philox/4 17 + uniforms 2 + Box-Muller 7.7 + lookup 6 + Euler 2 + store 1
 SLOTS_REV = 25.1    # per live path-step: load 1 + lookup 6 + slope 4 + c_n 6.1 + adjoint 2 + scatter 6
-# Linear spot axis, checkpointed (fused) kernel: the spot S = S0 exp(y) for the lookup
-# costs 5.1 (two multiplies and an exp) wherever a forward lookup is made.
-SLOTS_FUSED_ALL = 39.9    # every path-step: forward 35.7 - store 1 + exp 5.1 + checkpoint 1/16
-SLOTS_FUSED_LIVE = 57.8   # every live path-step: re-simulation 39.9 - 1/16 + c_n 1, and the
+# Linear spot axis, checkpointed (fused) kernel: e^y for the lookup costs 4.1 (a multiply
+# and an exp; the spot is folded into the axis scale) wherever a forward lookup is made.
+SLOTS_FUSED_ALL = 38.9    # every path-step: forward 35.7 - store 1 + exp 4.1 + checkpoint 1/16
+SLOTS_FUSED_LIVE = 56.8   # every live path-step: re-simulation 38.9 - 1/16 + c_n 1, and the
                           # reverse: lookup 6 + slope 3 + adjoint 2 + scatter 6 (the segment
-                          # keeps the re-simulation's spots, so no exp)
+                          # keeps the re-simulation's e^y, so no exp)
 BYTES_FWD = 4.0     # one FP32 state written per path-step
 BYTES_REV = 4.0     # one FP32 state read per live path-step
 

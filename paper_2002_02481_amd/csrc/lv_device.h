@@ -281,8 +281,8 @@ struct Look {
     bool in;   // strictly inside the spot range (slope is zero outside)
 };
 
-// Lookup at axis coordinate x (S on a linear axis, ln S on a log one) with offset
-// a_off: a = x / du + a_off is the grid coordinate.
+// Lookup at x with a = x inv_du + a_off the grid coordinate (x is S or S / spot on a
+// linear axis, ln(S / spot) on a log one, the caller scaling inv_du and a_off to match).
 template <typename R>
 __device__ __forceinline__ Look<R> lookup_at(R x, const R *trow, R inv_du, R a_off, R amax) {
     Look<R> L;
