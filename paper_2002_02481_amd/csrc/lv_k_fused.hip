@@ -194,8 +194,9 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 tcur = sg;
             }
             if (!wave_on) continue;   // no live path in this wave (the barriers above are the block's)
-            // this lane's histogram row of the segment's first step
-            Acc *const hseg = Hl + (na - hcur * WH) * KI1;
+            // this lane's histogram row of the segment's last step; the sweep steps it back
+            // one row per step
+            Acc *hrow = Hl + (na - hcur * WH + SEG - 1) * KI1;
             R ys[SEG], cs[SEG];
             R yy = CK[(size_t)sg * CH * slot_stride + sslot];
 #pragma unroll
@@ -259,9 +260,10 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         }
                         const R x = lam * cs[k];   // lam carries 2^F: x is the fixed-point term
                         lam = fma(x, dsd[r], (EX && RT) ? fma(lam, rdt, lam) : lam);
-                        scatter<R, false>(a, hseg + k * KI1, g64, n, L[r], x, qm, magic, inv_sc);
+                        scatter<R, false>(a, hrow, g64, n, L[r], x, qm, magic, inv_sc);
                         y_next = ys[k];
                     }
+                    hrow -= KI1;
                 }
             }
         }
