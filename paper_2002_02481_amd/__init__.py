@@ -130,7 +130,9 @@ def _surface_parts(surface, spot_axis, time_axis):
 # contexts
 # --------------------------------------------------------------------------
 class Context:
-    """A library context on one GPU: owns the device workspace and the graph cache."""
+    """A library context on one GPU: owns the device workspace, the graph cache and the
+    autotuner's choices (loaded from, and written back to, the file the environment
+    variable LVMC_TUNING_FILE names, if it is set when the context is created)."""
 
     def __init__(self, device: int = 0, stream: Optional[int] = None):
         self.lib = _lib_handle()
