@@ -811,7 +811,9 @@ lv_status save_tunings_merged(lv_ctx *ctx, const char *path) {
             const bool ours = sscanf(line, "%31s %d %63s %d %511s", tag, &ver, arch, &cus, key) == 5 &&
                               strcmp(tag, kTuneTag) == 0 && ver == kTuneVersion && ctx->arch == arch &&
                               cus == ctx->n_cu && ctx->tuned.count(key);
-            if (!ours && line[0] != '\n') keep.push_back(line);
+            if (ours || line[0] == '\n') continue;
+            keep.push_back(line);
+            if (keep.back().back() != '\n') keep.back() += '\n';   // a last line without one
         }
         fclose(f);
     }
