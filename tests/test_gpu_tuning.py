@@ -86,7 +86,7 @@ def test_tuning_file_named_by_the_environment(lv, tmp_path, monkeypatch):
     creation and takes the same shape; a file that is not a tuning file fails creation."""
     path = tmp_path / "tune_env.txt"
     foreign = "lvmc-tune 1 gfx000 7 some-other-request 512 2 16 1 512 2\n"
-    path.write_text(foreign)
+    path.write_text(foreign.rstrip("\n"))                  # a last line without its newline
     monkeypatch.setenv("LVMC_TUNING_FILE", str(path))
     a = lv.Context(0)
     res_a, shape_a = _call(lv, a, adjoint="stored", autotune=True)
