@@ -62,7 +62,7 @@ typedef enum {
     LV_ERR_STEP = 3,        /* a maturity is not a whole number of steps */
     LV_ERR_NOMEM = 4,       /* device workspace could not be allocated */
     LV_ERR_HIP = 5,         /* a HIP runtime call failed */
-    LV_ERR_UNSUPPORTED = 6  /* valid request this build does not handle (e.g. too many options) */
+    LV_ERR_UNSUPPORTED = 6  /* valid request the library does not handle (e.g. too many options) */
 } lv_status;
 
 enum { LV_AXIS_LIN = 0, LV_AXIS_LOG = 1 };
