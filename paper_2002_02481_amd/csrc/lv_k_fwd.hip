@@ -73,6 +73,7 @@ k_fwd(Args a) {
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)((unsigned long long)p >> 32);
         R y = EX ? spot : (R)0;
         int tap = 0, next_tap = a.n_taps > 0 ? a.tap_step[0] : -1;
+        R *sp = (R *)a.states + p;   // this path's stored state, one plane of P per step
         for (int wi = 0; wi < nW; ++wi) {
             const int ws = wi * W, we = min(N, ws + W);
             bool pending = false;
@@ -88,6 +89,7 @@ k_fwd(Args a) {
                     pending = true;
                 }
             }
+            const R *trow = tuse;   // the table row of step n, one row of I pairs per step
             for (int n0 = ws; n0 < we; n0 += 4) {
                 const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
                 R z[4];
@@ -97,10 +99,11 @@ k_fwd(Args a) {
                 for (int r = 0; r < 4; ++r) {
                     const int n = n0 + r;
                     if (n < N) {
-                        const R *trow = tuse + 2 * (n - ws) * I;
                         const Look<R> L = lookup_state<R, AXIS, EX>(y, trow, inv_du, a_off, inv_spot, amax, spot);
+                        trow += 2 * I;
                         y = step<R, EX, RT>(y, L.s, z[r], hdt, rdt);
-                        if (STORE && active) ((R *)a.states)[(size_t)n * a.P + p] = y;
+                        if (STORE && active) *sp = y;
+                        if (STORE) sp += a.P;
                         if (n + 1 == next_tap) {
                             fwd_payoffs<R, EX>(a, tap, y, active, wpart, wave, lane);
                             ++tap;
