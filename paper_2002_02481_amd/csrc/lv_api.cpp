@@ -804,8 +804,9 @@ void write_tuning_line(FILE *f, const lv_ctx *ctx, const std::string &key, const
 lv_status save_tunings_merged(lv_ctx *ctx, const char *path) {
     std::vector<std::string> keep;
     if (FILE *f = fopen(path, "r")) {
-        char line[1024];
-        while (fgets(line, sizeof line, f)) {
+        char *line = nullptr;   // whole lines of any length (getline grows the buffer)
+        size_t cap = 0;
+        while (getline(&line, &cap, f) > 0) {
             char tag[32], arch[64], key[512];
             int ver = 0, cus = 0;
             const bool ours = sscanf(line, "%31s %d %63s %d %511s", tag, &ver, arch, &cus, key) == 5 &&
@@ -815,6 +816,7 @@ lv_status save_tunings_merged(lv_ctx *ctx, const char *path) {
             keep.push_back(line);
             if (keep.back().back() != '\n') keep.back() += '\n';   // a last line without one
         }
+        free(line);
         fclose(f);
     }
     const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
@@ -1427,10 +1429,11 @@ lv_status lv_tuning_load(lv_ctx *ctx, const char *path, int32_t *n_out) {
     if (!ctx || !path) return fail(ctx, LV_ERR_ARG, "ctx and path are required");
     FILE *f = fopen(path, "r");
     if (!f) return fail(ctx, LV_ERR_ARG, "cannot read %s", path);
-    char line[1024];
+    char *line = nullptr;   // whole lines of any length (getline grows the buffer)
+    size_t cap = 0;
     int n = 0, lineno = 0;
     lv_status st = LV_OK;
-    while (fgets(line, sizeof line, f)) {
+    while (getline(&line, &cap, f) > 0) {
         ++lineno;
         if (line[0] == '\n' || line[0] == '#') continue;
         char tag[32], arch[64], key[512];
@@ -1454,6 +1457,7 @@ lv_status lv_tuning_load(lv_ctx *ctx, const char *path, int32_t *n_out) {
         ctx->tuned[key] = c;
         ++n;
     }
+    free(line);
     fclose(f);
     if (st != LV_OK) return st;
     if (n_out) *n_out = n;

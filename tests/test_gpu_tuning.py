@@ -85,7 +85,7 @@ def test_tuning_file_named_by_the_environment(lv, tmp_path, monkeypatch):
     there, keeping the lines of other devices; a later context loads the file at
     creation and takes the same shape; a file that is not a tuning file fails creation."""
     path = tmp_path / "tune_env.txt"
-    foreign = "lvmc-tune 1 gfx000 7 some-other-request 512 2 16 1 512 2\n"
+    foreign = "lvmc-tune 1 gfx000 7 " + "k" * 500 + " 512 2 16 1 512 2  " + "#" * 1500 + "\n"   # 2 KB
     path.write_text(foreign.rstrip("\n"))                  # a last line without its newline
     monkeypatch.setenv("LVMC_TUNING_FILE", str(path))
     a = lv.Context(0)
