@@ -150,7 +150,8 @@ typedef struct {
 enum { LV_SCHEME_LOG_EULER = 0, LV_SCHEME_EULER_X = 1 };
 
 /* Create a context on HIP device `device` that launches on `hip_stream`
- * (a hipStream_t; NULL = the null stream).  The context owns a device
+ * (a hipStream_t; NULL = a stream the context creates, which, like every stream
+ * made without flags, is ordered with the null stream).  The context owns a device
  * workspace that grows on demand and is freed by lv_destroy.  If the environment
  * variable LVMC_TUNING_FILE names a file, lv_create loads the saved tunings in it
  * (as lv_tuning_load; a file that is not a tuning file fails lv_create with
@@ -160,6 +161,9 @@ enum { LV_SCHEME_LOG_EULER = 0, LV_SCHEME_EULER_X = 1 };
  * written beside it (a failure to write fails the autotuned call with LV_ERR_ARG). */
 lv_status lv_create(lv_ctx **out, int device, void *hip_stream);
 void lv_destroy(lv_ctx *ctx);
+/* Launch later calls on `hip_stream` (NULL as for lv_create).  When the stream
+ * changes, the call first waits for the work queued on the previous one, which may
+ * still use the context's buffers; LV_ERR_HIP if that wait fails. */
 lv_status lv_set_stream(lv_ctx *ctx, void *hip_stream);
 
 /* Message of the last failed call on ctx (ctx may be NULL: the last failure of

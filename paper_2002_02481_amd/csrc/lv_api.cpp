@@ -1020,7 +1020,13 @@ void lv_destroy(lv_ctx *ctx) {
 
 lv_status lv_set_stream(lv_ctx *ctx, void *hip_stream) {
     if (!ctx) return fail(nullptr, LV_ERR_ARG, "ctx is NULL");
+    const hipStream_t prev = ctx->stream();
     ctx->user_stream = (hipStream_t)hip_stream;
+    if (ctx->stream() != prev) {
+        // work queued on the previous stream may still use the context's buffers
+        HIPCHECK(ctx, hipSetDevice(ctx->device));
+        HIPCHECK(ctx, hipStreamSynchronize(prev));
+    }
     return LV_OK;
 }
 
