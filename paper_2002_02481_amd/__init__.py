@@ -272,6 +272,47 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _need_dev(t, name, device=None, numel=None, dtype=None, nbytes=None):
+    """The library takes plain device pointers and trusts their extent, so every tensor
+    it is given is checked here first: a contiguous CUDA tensor (on `device`, of
+    `dtype`, float64 unless given, with at least `numel` elements or `nbytes` bytes);
+    ValueError otherwise."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}; the call runs on {device}")
+    if nbytes is None and t.dtype != (dtype or torch.float64):
+        raise ValueError(f"{name} must be {dtype or torch.float64}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements; {numel} are needed")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes; {nbytes} are needed")
+    return t
+
+
+def _need_surface(sigma, grid, batched):
+    """sigma: [I, J] (or [n_surf, I, J] when batched; [I, J] is one surface) matching
+    the grid's axes; returns it in the shape the call takes."""
+    _need_dev(sigma, "sigma")
+    if batched and sigma.dim() == 2:
+        sigma = sigma.unsqueeze(0)
+    want = (grid.spot.n, grid.time.n)
+    if sigma.dim() != (3 if batched else 2) or tuple(sigma.shape[-2:]) != want:
+        raise ValueError(f"sigma has shape {tuple(sigma.shape)}; the grid's axes give "
+                         f"{'[n_surf, ' if batched else '['}{want[0]}, {want[1]}]")
+    return sigma
+
+
+def _ctx_for(ctx, t):
+    ctx = ctx or default_context(t.device.index or 0)
+    if ctx.device != (t.device.index or 0):
+        raise ValueError(f"the context is on cuda:{ctx.device}, the tensors on {t.device}")
+    return ctx
+
+
 def price_and_grad_dev(sigmas, spot, strikes, maturities, n_paths, n_steps, seed=0, *, spot_axis,
                        time_axis, is_put=None, weights=None, want_grad=True, out=None,
                        ctx: Optional[Context] = None, **opts):
@@ -279,13 +320,11 @@ def price_and_grad_dev(sigmas, spot, strikes, maturities, n_paths, n_steps, seed
     [n_surf, I, J].  Returns (prices, std_errs, grads, deltas) CUDA tensors; nothing
     is synchronised.  `out` may pass preallocated tensors in that order."""
     import torch
-    ctx = ctx or default_context(sigmas.device.index or 0)
-    ctx.use_torch_stream()
-    if sigmas.dim() == 2:
-        sigmas = sigmas.unsqueeze(0)
-    assert sigmas.is_cuda and sigmas.dtype == torch.float64 and sigmas.is_contiguous()
-    n_surf, I, J = sigmas.shape
     grid = make_grid(spot_axis, time_axis)
+    sigmas = _need_surface(sigmas, grid, batched=True)
+    ctx = _ctx_for(ctx, sigmas)
+    ctx.use_torch_stream()
+    n_surf, I, J = sigmas.shape
     book = _Book(strikes, maturities, is_put, weights)
     o = make_opts(**opts)
     adjoint = want_grad and o.adjoint != _lib.LV_ADJ_NONE
@@ -297,6 +336,14 @@ def price_and_grad_dev(sigmas, spot, strikes, maturities, n_paths, n_steps, seed
         deltas = torch.empty((n_surf,), dtype=torch.float64, device=dev) if adjoint else None
     else:
         prices, stderrs, grads, deltas = out
+        _need_dev(prices, "prices", dev, n_surf * book.n)
+        _need_dev(stderrs, "std_errs", dev, n_surf * book.n)
+        if not adjoint:
+            grads = deltas = None
+        if grads is not None:
+            _need_dev(grads, "grads", dev, n_surf * I * J)
+        if deltas is not None:
+            _need_dev(deltas, "deltas", dev, n_surf)
     st = ctx.lib.lv_price_and_grad_dev(
         ctx.h, C.byref(grid), n_surf, _ptr(sigmas), float(spot), C.byref(book.c), int(n_paths),
         int(n_steps), int(seed), C.byref(o), _ptr(prices), _ptr(stderrs), _ptr(grads), _ptr(deltas))
@@ -310,22 +357,23 @@ def price_and_grad_noalloc(sigmas, spot, strikes, maturities, n_paths, n_steps, 
     """price_and_grad_dev through the allocation-free entry point: the library works in
     its fixed per-GPU workspace and allocates nothing.  `out` = (prices, std_errs, grads,
     deltas) CUDA float64 tensors the caller allocated (grads and deltas may be None)."""
-    import torch
-    ctx = ctx or default_context(sigmas.device.index or 0)
-    ctx.use_torch_stream()
-    if sigmas.dim() == 2:
-        sigmas = sigmas.unsqueeze(0)
-    assert sigmas.is_cuda and sigmas.dtype == torch.float64 and sigmas.is_contiguous()
-    n_surf = sigmas.shape[0]
     grid = make_grid(spot_axis, time_axis)
+    sigmas = _need_surface(sigmas, grid, batched=True)
+    ctx = _ctx_for(ctx, sigmas)
+    ctx.use_torch_stream()
+    n_surf, I, J = sigmas.shape
     book = _Book(strikes, maturities, is_put, weights)
     o = make_opts(**opts)
     prices, stderrs, grads, deltas = out
-    if not want_grad:
+    if not want_grad or o.adjoint == _lib.LV_ADJ_NONE:
         grads = deltas = None
-    for t in (prices, stderrs, grads, deltas):
-        assert t is None or (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous())
-    assert prices.numel() >= n_surf * book.n and stderrs.numel() >= n_surf * book.n
+    dev = sigmas.device
+    _need_dev(prices, "prices", dev, n_surf * book.n)
+    _need_dev(stderrs, "std_errs", dev, n_surf * book.n)
+    if grads is not None:
+        _need_dev(grads, "grads", dev, n_surf * I * J)
+    if deltas is not None:
+        _need_dev(deltas, "deltas", dev, n_surf)
     st = ctx.lib.lv_price_and_grad_noalloc(
         ctx.h, C.byref(grid), n_surf, _ptr(sigmas), float(spot), C.byref(book.c), int(n_paths),
         int(n_steps), int(seed), C.byref(o), _ptr(prices), _ptr(stderrs), _ptr(grads), _ptr(deltas))
@@ -340,13 +388,16 @@ def bump_grad_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed=0, *,
     width eps on every node (same paths as the adjoint), for comparison with it.
     sigma is a CUDA float64 tensor [I, J]; runs on torch's current stream."""
     import torch
-    ctx = ctx or default_context(sigma.device.index or 0)
-    ctx.use_torch_stream()
-    assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
     grid = make_grid(spot_axis, time_axis)
+    sigma = _need_surface(sigma, grid, batched=False)
+    ctx = _ctx_for(ctx, sigma)
+    ctx.use_torch_stream()
     book = _Book(strikes, maturities, is_put, weights)
     o = make_opts(**opts)
-    grad = out if out is not None else torch.empty(sigma.shape[-2:], dtype=torch.float64, device=sigma.device)
+    if out is not None:
+        grad = _need_dev(out, "out", sigma.device, sigma.numel())
+    else:
+        grad = torch.empty(sigma.shape, dtype=torch.float64, device=sigma.device)
     st = ctx.lib.lv_bump_grad_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),
                                   int(n_paths), int(n_steps), int(seed), C.byref(o), float(eps),
                                   int(batch), _ptr(grad))
@@ -361,7 +412,8 @@ def per_option_grads_dev(sigma, spot, strikes, maturities, n_paths, n_steps, see
     with its own adjoint (seeded by its own payoff) and its own gradient histogram.
     Returns (prices [n], std_errs [n], grads [n, I, J], deltas [n]) CUDA tensors."""
     import torch
-    ctx = ctx or default_context(sigma.device.index or 0)
+    sigma = _need_surface(sigma, make_grid(spot_axis, time_axis), batched=False)
+    ctx = _ctx_for(ctx, sigma)
     price, stderr, states = forward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed,
                                         spot_axis=spot_axis, time_axis=time_axis, is_put=is_put,
                                         precision=precision, rate=rate, ctx=ctx)
@@ -387,14 +439,15 @@ def forward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, *, spo
                 is_put=None, precision=32, rate=0.0, states=None, ctx: Optional[Context] = None):
     """Split forward: returns (price, std_err, states) CUDA tensors."""
     import torch
-    ctx = ctx or default_context(sigma.device.index or 0)
-    ctx.use_torch_stream()
     grid = make_grid(spot_axis, time_axis)
+    sigma = _need_surface(sigma, grid, batched=False)
+    ctx = _ctx_for(ctx, sigma)
+    ctx.use_torch_stream()
     book = _Book(strikes, maturities, is_put, None)
     nb = states_bytes(precision, n_paths, n_steps)
     if states is None:
         states = torch.empty(nb, dtype=torch.uint8, device=sigma.device)
-    assert states.numel() * states.element_size() >= nb
+    _need_dev(states, "states", sigma.device, nbytes=nb)
     price = torch.empty(book.n, dtype=torch.float64, device=sigma.device)
     stderr = torch.empty_like(price)
     st = ctx.lib.lv_forward_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),
@@ -409,11 +462,15 @@ def backward_dev(sigma, spot, strikes, maturities, n_paths, n_steps, seed, state
                  ctx: Optional[Context] = None):
     """Split backward: gradient [I, J] of sum_k cotangent_k price_k (and delta)."""
     import torch
-    ctx = ctx or default_context(sigma.device.index or 0)
-    ctx.use_torch_stream()
     grid = make_grid(spot_axis, time_axis)
+    sigma = _need_surface(sigma, grid, batched=False)
+    ctx = _ctx_for(ctx, sigma)
+    ctx.use_torch_stream()
     book = _Book(strikes, maturities, is_put, None)
-    cot = cotangent.to(dtype=torch.float64).contiguous()
+    _need_dev(states, "states", sigma.device, nbytes=states_bytes(precision, n_paths, n_steps))
+    cot = torch.as_tensor(cotangent, dtype=torch.float64, device=sigma.device).contiguous().reshape(-1)
+    if cot.numel() != book.n:
+        raise ValueError(f"cotangent has {cot.numel()} entries for a book of {book.n} options")
     grad = torch.empty(sigma.shape, dtype=torch.float64, device=sigma.device)
     delta = torch.empty(1, dtype=torch.float64, device=sigma.device) if want_delta else None
     st = ctx.lib.lv_backward_dev(ctx.h, C.byref(grid), _ptr(sigma), float(spot), C.byref(book.c),

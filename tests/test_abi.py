@@ -208,3 +208,23 @@ def test_rate_is_validated():
     assert lv.check(**_req(), rate=-1.0) == _lib.LV_OK
     for bad in (float("nan"), float("inf"), 1.5, -2.0):
         assert lv.check(**_req(), rate=bad) == _lib.LV_ERR_ARG
+
+
+def test_device_calls_refuse_host_tensors():
+    """The calls that hand device pointers to the library check every tensor before a
+    context is made or anything is launched: host tensors are refused (no GPU needed)."""
+    import torch
+    s = W.small_surface()
+    ax = dict(spot_axis=s.spot_axis, time_axis=s.time_axis)
+    sig = torch.tensor(s.sigma, dtype=torch.float64)
+    calls = [
+        lambda: lv.price_and_grad_dev(sig, 100.0, [100.0], [1.0], 1024, 52, **ax),
+        lambda: lv.price_and_grad_noalloc(sig, 100.0, [100.0], [1.0], 1024, 52, out=(None,) * 4, **ax),
+        lambda: lv.bump_grad_dev(sig, 100.0, [100.0], [1.0], 1024, 52, **ax),
+        lambda: lv.forward_dev(sig, 100.0, [100.0], [1.0], 1024, 52, 0, **ax),
+        lambda: lv.backward_dev(sig, 100.0, [100.0], [1.0], 1024, 52, 0, None, [1.0], **ax),
+        lambda: lv.per_option_grads_dev(sig, 100.0, [100.0], [1.0], 1024, 52, **ax),
+    ]
+    for k, f in enumerate(calls):
+        with pytest.raises(ValueError, match="CUDA tensor"):
+            f()

@@ -46,3 +46,38 @@ def test_state_buffer_beyond_hbm_is_nomem_and_the_context_recovers(lv):
     fresh = _small(lv, lv.Context(0))
     for a, b, c in zip(before, after, fresh):
         assert np.array_equal(a, b) and np.array_equal(b, c)
+
+
+def test_device_tensors_are_checked_before_anything_runs(lv):
+    """The binding hands the library plain device pointers, so it checks each tensor's
+    type, shape, layout and extent first: a wrong one is a ValueError, nothing is
+    launched, and the context then prices as a fresh one does."""
+    import torch
+    wl = W.small_call()
+    s, b = wl.surface, wl.book
+    ax = dict(spot_axis=s.spot_axis, time_axis=s.time_axis)
+    sig = torch.tensor(s.sigma, dtype=torch.float64, device="cuda")
+    ctx = lv.Context(0)
+    args = (100.0, b.strike, b.maturity, wl.n_paths, wl.n_steps, wl.seed)
+    small = torch.empty(0, dtype=torch.float64, device="cuda")
+    one = torch.empty(1, dtype=torch.float64, device="cuda")
+    _, _, states = lv.forward_dev(sig, *args, ctx=ctx, **ax)
+    torch.cuda.synchronize()
+    bad = [
+        (lambda: lv.price_and_grad_dev(sig.float(), *args, ctx=ctx, **ax), "float64"),
+        (lambda: lv.price_and_grad_dev(sig[:-1], *args, ctx=ctx, **ax), "shape"),
+        (lambda: lv.price_and_grad_dev(sig.t(), *args, ctx=ctx, **ax), "contiguous"),
+        (lambda: lv.price_and_grad_dev(sig, *args, ctx=ctx, out=(small, one, None, None), **ax), "are needed"),
+        (lambda: lv.bump_grad_dev(sig, *args, ctx=ctx, out=small, **ax), "are needed"),
+        (lambda: lv.forward_dev(sig, *args, ctx=ctx, states=torch.empty(16, dtype=torch.uint8, device="cuda"),
+                                **ax), "bytes"),
+        (lambda: lv.backward_dev(sig, *args, states[:16], [1.0], ctx=ctx, **ax), "bytes"),
+        (lambda: lv.backward_dev(sig, *args, states, [1.0, 2.0], ctx=ctx, **ax), "cotangent"),
+    ]
+    for k, (f, msg) in enumerate(bad):
+        with pytest.raises(ValueError, match=msg):
+            f()
+    got = _small(lv, ctx)
+    ref = _small(lv, lv.Context(0))
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
