@@ -222,50 +222,56 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                     }
                 }
             }
+            auto sweep = [&](auto notap_tag) {
+                constexpr bool NOTAP = decltype(notap_tag)::value;
 #pragma unroll
-            for (int q2 = SEG / 2 - 1; q2 >= 0; --q2) {
-                // lookups of two steps first (independent of lambda), then the chain; pairs
-                // rather than fours keep the 16-step segment within 128 VGPRs (no spills)
-                Look<R> L[2];
-                R dsd[2];
+                for (int q2 = SEG / 2 - 1; q2 >= 0; --q2) {
+                    // lookups of two steps first (independent of lambda), then the chain; pairs
+                    // rather than fours keep the 16-step segment within 128 VGPRs (no spills)
+                    Look<R> L[2];
+                    R dsd[2];
 #pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    const int k = 2 * q2 + r;
-                    if (na + k < N) {
-                        if (HS) {
-                            // d sigma / d y = (d / du) S = (d / du') E
-                            L[r] = lookup_at<R>(ys[k], tab + 2 * k * I, s_inv_du, a_off, amax);
-                            dsd[r] = L[r].in ? L[r].d * s_inv_du * ys[k] : (R)0;
-                        } else {
-                            L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off,
-                                                             inv_spot, amax, spot);
-                            R d = L[r].in ? L[r].d * inv_du : (R)0;
-                            if (AXIS == 0) d *= L[r].S;
-                            // EX: sigma / X + d sigma / d X (on a log axis d sigma / d X = (d / du) / X)
-                            dsd[r] = EX ? (L[r].s + d) * Math<R>::rcp(ys[k]) : d;
+                    for (int r = 0; r < 2; ++r) {
+                        const int k = 2 * q2 + r;
+                        if (NOTAP || na + k < N) {
+                            if (HS) {
+                                // d sigma / d y = (d / du) S = (d / du') E
+                                L[r] = lookup_at<R>(ys[k], tab + 2 * k * I, s_inv_du, a_off, amax);
+                                dsd[r] = L[r].in ? L[r].d * s_inv_du * ys[k] : (R)0;
+                            } else {
+                                L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off,
+                                                                 inv_spot, amax, spot);
+                                R d = L[r].in ? L[r].d * inv_du : (R)0;
+                                if (AXIS == 0) d *= L[r].S;
+                                // EX: sigma / X + d sigma / d X (on a log axis d sigma / d X = (d / du) / X)
+                                dsd[r] = EX ? (L[r].s + d) * Math<R>::rcp(ys[k]) : d;
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int r = 1; r >= 0; --r) {
-                    const int k = 2 * q2 + r;
-                    const int n = na + k;
-                    if (n < N) {
-                        if (n + 1 == cur_tap) {
-                            lam = HS ? rev_seeds_at<R, EX>(a, rtap, spot * y_next, lam, scd)
-                                     : rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
-                            if (!on) lam = 0;
-                            --rtap;
-                            cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+                    for (int r = 1; r >= 0; --r) {
+                        const int k = 2 * q2 + r;
+                        const int n = na + k;
+                        if (NOTAP || n < N) {
+                            if (!NOTAP && n + 1 == cur_tap) {
+                                lam = HS ? rev_seeds_at<R, EX>(a, rtap, spot * y_next, lam, scd)
+                                         : rev_seeds<R, EX>(a, rtap, y_next, lam, scd);
+                                if (!on) lam = 0;
+                                --rtap;
+                                cur_tap = rtap >= 0 ? a.tap_step[rtap] : -1;
+                            }
+                            const R x = lam * cs[k];   // lam carries 2^F: x is the fixed-point term
+                            lam = fma(x, dsd[r], (EX && RT) ? fma(lam, rdt, lam) : lam);
+                            scatter<R, false>(a, hrow, g64, n, L[r], x, qm, magic, inv_sc);
+                            y_next = ys[k];
                         }
-                        const R x = lam * cs[k];   // lam carries 2^F: x is the fixed-point term
-                        lam = fma(x, dsd[r], (EX && RT) ? fma(lam, rdt, lam) : lam);
-                        scatter<R, false>(a, hrow, g64, n, L[r], x, qm, magic, inv_sc);
-                        y_next = ys[k];
+                        hrow -= KI1;
                     }
-                    hrow -= KI1;
                 }
-            }
+            };
+            // a segment with no tap step among its steps' successors runs without the tests
+            if (nw == SEG && !(cur_tap > na && cur_tap <= na + SEG)) sweep(std::true_type{});
+            else sweep(std::false_type{});
         }
         __syncthreads();
         fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
