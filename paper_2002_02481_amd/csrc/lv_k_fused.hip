@@ -107,31 +107,37 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                 __syncthreads();
                 tcur = sg;
             }
+            // a segment whose steps reach no tap step runs without the per-step tests
+            auto fseg = [&](auto notap_tag) {
+                constexpr bool NOTAP = decltype(notap_tag)::value;
 #pragma unroll
-            for (int q4 = 0; q4 < SEG / 4; ++q4) {
-                const int n0 = na + 4 * q4;
-                if (n0 < N) {
-                    const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
-                    R z[4];
-                    Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
-                    Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
+                for (int q4 = 0; q4 < SEG / 4; ++q4) {
+                    const int n0 = na + 4 * q4;
+                    if (NOTAP || n0 < N) {
+                        const Words w = philox10((uint32_t)(n0 >> 2), 0u, plo, phi, a.key0, a.key1);
+                        R z[4];
+                        Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
+                        Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int n = n0 + r;
-                        if (n < N) {
-                            const Look<R> L = lookup_state<R, AXIS, EX>(y, tab + 2 * (4 * q4 + r) * I,
-                                                                        inv_du, a_off, inv_spot, amax, spot);
-                            y = step<R, EX, RT>(y, L.s, z[r], hdt, rdt);
-                            if (n + 1 == next_tap) {
-                                fwd_payoffs<R, EX>(a, tap, y, active, wpart, wave, lane);
-                                if (!lv) lv = tap_live<R, EX>(a, tap, y);
-                                ++tap;
-                                next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                        for (int r = 0; r < 4; ++r) {
+                            const int n = n0 + r;
+                            if (NOTAP || n < N) {
+                                const Look<R> L = lookup_state<R, AXIS, EX>(y, tab + 2 * (4 * q4 + r) * I,
+                                                                            inv_du, a_off, inv_spot, amax, spot);
+                                y = step<R, EX, RT>(y, L.s, z[r], hdt, rdt);
+                                if (!NOTAP && n + 1 == next_tap) {
+                                    fwd_payoffs<R, EX>(a, tap, y, active, wpart, wave, lane);
+                                    if (!lv) lv = tap_live<R, EX>(a, tap, y);
+                                    ++tap;
+                                    next_tap = tap < a.n_taps ? a.tap_step[tap] : -1;
+                                }
                             }
                         }
                     }
                 }
-            }
+            };
+            if (nw == SEG && !(next_tap > na && next_tap <= na + SEG)) fseg(std::true_type{});
+            else fseg(std::false_type{});
         }
         // ---- queue the tile's live paths behind those already waiting
         const bool live = active && (a.dense || lv);
@@ -199,29 +205,34 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
             Acc *hrow = Hl + (na - hcur * WH + SEG - 1) * KI1;
             R ys[SEG], cs[SEG];
             R yy = CK[(size_t)sg * CH * slot_stride + sslot];
+            auto resim = [&](auto full_tag) {
+                constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
-            for (int q4 = 0; q4 < SEG / 4; ++q4) {
-                const int n0 = na + 4 * q4;
-                if (n0 < N) {
-                    const Words w = philox10((uint32_t)(n0 >> 2), 0u, slo, shi, a.key0, a.key1);
-                    R z[4];
-                    Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
-                    Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
+                for (int q4 = 0; q4 < SEG / 4; ++q4) {
+                    const int n0 = na + 4 * q4;
+                    if (FULL || n0 < N) {
+                        const Words w = philox10((uint32_t)(n0 >> 2), 0u, slo, shi, a.key0, a.key1);
+                        R z[4];
+                        Math<R>::box_muller(w.x, w.y, sdt, z[0], z[1]);
+                        Math<R>::box_muller(w.z, w.w, sdt, z[2], z[3]);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int k = 4 * q4 + r;
-                        if (n0 + r < N) {
-                            const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
-                                                                        inv_spot, amax, spot);
-                            ys[k] = HS ? L.E : yy;
-                            // the forward's own arithmetic, so the re-simulated states (and
-                            // with them the seed tests) are the forward's bit for bit
-                            cs[k] = EX ? yy * z[r] : fma((R)-2 * hdt, L.s, z[r]);
-                            yy = step<R, EX, RT>(yy, L.s, z[r], hdt, rdt);
+                        for (int r = 0; r < 4; ++r) {
+                            const int k = 4 * q4 + r;
+                            if (FULL || n0 + r < N) {
+                                const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
+                                                                            inv_spot, amax, spot);
+                                ys[k] = HS ? L.E : yy;
+                                // the forward's own arithmetic, so the re-simulated states (and
+                                // with them the seed tests) are the forward's bit for bit
+                                cs[k] = EX ? yy * z[r] : fma((R)-2 * hdt, L.s, z[r]);
+                                yy = step<R, EX, RT>(yy, L.s, z[r], hdt, rdt);
+                            }
                         }
                     }
                 }
-            }
+            };
+            if (nw == SEG) resim(std::true_type{});
+            else resim(std::false_type{});
             auto sweep = [&](auto notap_tag) {
                 constexpr bool NOTAP = decltype(notap_tag)::value;
 #pragma unroll
