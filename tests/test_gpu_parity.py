@@ -294,6 +294,31 @@ def test_sigma_bf16(lv, ctx, orc, precision):
             assert np.array_equal(g["price"], want["price"]) and np.array_equal(g["grad"], want["grad"])
 
 
+def segment_edge_book(seg):
+    """Options whose maturities fall on the last step of a checkpoint segment, on the
+    first step of the next one, and between, with a horizon that ends mid-segment: the
+    segments a sweep or forward takes without tap tests sit beside those it cannot."""
+    steps = [seg, seg + 1, 2 * seg, 3 * seg - 1, 3 * seg + 1, 4 * seg + 3]   # of 4 seg + 3, over one year
+    k = np.arange(len(steps))
+    return W.Book((k % 2).astype(np.int32), 90.0 + 4.0 * k, np.array(steps) / (4.0 * seg + 3.0),
+                  np.where(k % 3 == 2, -0.5, 1.0))
+
+
+@pytest.mark.parametrize("precision,seg", [(32, 16), (64, 16), (32, 8), (64, 32)])
+def test_checkpoint_taps_at_segment_edges(lv, ctx, orc, precision, seg):
+    """The checkpointed kernel runs segments whose steps reach no payoff date without
+    the per-step tests: maturities on and beside segment boundaries, and a ragged last
+    segment, against the oracle."""
+    book = segment_edge_book(seg)
+    N = 4 * seg + 3
+    surf = W.small_surface()
+    s = surf.rounded_to_f32() if precision == 32 else surf
+    ref = orc.price_and_grad(s, book, 20000 + 11, N, seed=5)
+    got = gpu_run(lv, ctx, surf, book, 20000 + 11, N, 5, precision=precision, adjoint="checkpoint",
+                  ckpt_every=seg)
+    assert_parity(got, ref, precision, f"segment-edge taps FP{precision} seg {seg}")
+
+
 @pytest.mark.parametrize("precision,axis,seg", [(32, "lin", 16), (64, "lin", 8), (32, "log", 32),
                                                (64, "log", 16)])
 def test_euler_x_checkpoint(lv, ctx, orc, precision, axis, seg):
