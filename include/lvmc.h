@@ -112,7 +112,8 @@ typedef struct {
     int32_t copies;         /* privatised copies of the LDS gradient histogram (1..16); 0 = default */
     int32_t window;         /* steps per LDS vol-table window (multiple of 8 in [8, 64]); the gradient
                                histogram spans the largest multiple of it that the LDS budget of
-                               blocks_per_cu blocks allows (up to the whole horizon); 0 = default */
+                               blocks_per_cu blocks allows (up to the whole horizon); 0 = default.
+                               The checkpointed kernel plans its own: 1, 2 or 4 segments */
     int32_t profile;        /* 1: time every kernel with hipEvents (eager launches only), read back
                                with lv_kernel_times */
     int32_t autotune;       /* 1: on the first call of a shape (grid, steps, paths, book size,
@@ -307,7 +308,8 @@ typedef struct {
     int32_t precision;
     int32_t graph_replayed;     /* 1 if the last call replayed a captured graph */
     int32_t copies;             /* histogram copies of the launch */
-    int32_t window;             /* steps per LDS table window (the segment for the checkpoint kernel) */
+    int32_t window;             /* steps per LDS table window (for the checkpoint kernel 1, 2 or 4
+                                   segments, as many as its LDS holds) */
     int32_t blocks_per_cu;      /* persistent blocks per CU asked for */
     int32_t autotuned;          /* 1 if the shape came from the autotuner */
     int32_t fwd_block;          /* threads per block of the separate forward kernel */

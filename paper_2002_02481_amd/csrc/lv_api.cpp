@@ -45,6 +45,7 @@ struct Plan {
     std::vector<double> ta, opt_strike, weight, opt_disc;   // opt_disc: e^{-r T_k}, tap order
     double rate = 0;
     int precision = 32, adjoint = LV_ADJ_STORED, seg = 16, profile = 0;   // profile: kinds to time (bits)
+    int tws = 1;   // checkpointed: segments per vol-table window (1, 2 or 4)
     int block = 256, blocks = 0, n_tiles = 0, W = 16, WH = 16, K = 8, bpc = 2, CH = 1;
     int dense = 0;   // reverse kernel sweeps every path (not only those with a nonzero adjoint)
     int scheme = 0;  // 0: Euler on ln X; 1: Euler on X
@@ -145,7 +146,9 @@ long long floor_pow2(long long x) {
 
 // Table window of the adjoint (or fused) kernel: the checkpoint segment for the
 // fused kernel.
-int table_window(const Plan &pl, const Shape &sh) { return pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg : sh.W; }
+int table_window(const Plan &pl, const Shape &sh) {
+    return pl.adjoint == LV_ADJ_CHECKPOINT ? pl.seg * pl.tws : sh.W;
+}
 
 // Path tiles per live-path list of the stored reverse kernel (all of a block's
 // tiles, up to 4), and checkpoint slot sets in the fused kernel's ring (up to 4: each
@@ -214,6 +217,14 @@ Shape default_shape(const Plan &pl, int n_cu) {
 lv_status apply_shape(lv_ctx *ctx, Plan &pl, Shape sh, int n_cu, size_t max_lds, bool may_shrink_k,
                       bool may_shrink_w) {
     const bool ckpt = pl.adjoint == LV_ADJ_CHECKPOINT;
+    if (ckpt) {
+        // the fused kernel stages the vol table up to four segments at a time (fewer block
+        // barriers and table copies): as many as the horizon uses and the block's LDS holds
+        // beside the smallest histogram window
+        pl.tws = 4;
+        while (pl.tws > 1 && (long long)pl.seg * (pl.tws / 2) >= pl.N) pl.tws /= 2;
+        while (pl.tws > 1 && !shape_fits(pl, sh, max_lds, n_cu)) pl.tws /= 2;
+    }
     while (!shape_fits(pl, sh, max_lds, n_cu) && sh.W > 8 && may_shrink_w && !ckpt) sh.W /= 2;
     while (!shape_fits(pl, sh, max_lds, n_cu) && sh.K > 1 && may_shrink_k) sh.K /= 2;
     if (!shape_fits(pl, sh, max_lds, n_cu))

@@ -12,9 +12,10 @@ namespace lvk {
 // axis e^y = S / spot) and c_n = -sigma_n dt + sqrt(dt) Z_n held in registers, and
 // swept backwards.
 // Checkpoints live in per-block slots reused by every tile of the block.  The
-// LDS table holds one segment; consecutive uses of the same segment (the last
-// one forward then backward, the first one backward then forward for the next
-// tile) share its copy.  The block's tiles b, b + B, ... are run forward one at a
+// LDS table holds a window of one, two or four segments (as many as the block's LDS
+// allows beside the histogram; fewer copies and barriers); consecutive uses of the
+// same window (the last one forward then backward, the first one backward then
+// forward for the next tile) share its copy.  The block's tiles b, b + B, ... are run forward one at a
 // time, each into the next of CH checkpoint slot sets; only their live paths (an
 // option with a nonzero cotangent in the money at its maturity, as in the stored
 // reverse kernel; every path with a.dense) are swept back, queued in path order
@@ -35,7 +36,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     // on it (a wave with no queued path skips the sweep) and all that follows them uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int I = a.I, J = a.J, N = a.N, G = I * J, WH = a.WH;
-    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, SEG, WH, a.K, a.CH);
+    const Lds lay = lds_layout(FUSED_CKPT, sizeof(R), sizeof(Acc), I, J, a.n_opt, wpb, a.W, WH, a.K, a.CH);
     double *g64 = (double *)(smem + lay.g64);
     double *wpart = (double *)(smem + lay.wpart);
     double *wlam = (double *)(smem + lay.wlam);
@@ -70,7 +71,10 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
     const size_t slot_stride = (size_t)gridDim.x * blockDim.x;
     const size_t slot = (size_t)blockIdx.x * blockDim.x + tid;
     TabStage<R> stg;
-    int tcur = -1;   // segment whose table is in LDS
+    // The LDS table holds a window of a.W steps, 2^tsh segments (the planner's choice):
+    // segment sg has its rows at (sg mod 2^tsh) SEG in window sg >> tsh.
+    const int tsh = __builtin_ctz((unsigned)(a.W / SEG));
+    int tcur = -1;   // table window in LDS
 
     // queue positions (monotone; entry q sits at q mod QCAP), the queue position after
     // each slot set's tile was listed, tiles forwarded, and the oldest forwarded tile
@@ -100,13 +104,14 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         for (int sg = 0; sg < n_seg; ++sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
             CK[(size_t)(sg * CH + ss) * slot_stride + slot] = y;
-            if (sg != tcur) {
+            if ((sg >> tsh) != tcur) {
                 __syncthreads();
-                stg.issue(a, na, nw);
+                stg.issue(a, (sg >> tsh) * a.W, min(a.W, N - (sg >> tsh) * a.W));
                 stg.commit(a, tab);
                 __syncthreads();
-                tcur = sg;
+                tcur = sg >> tsh;
             }
+            const R *tt = tab + (sg & ((1 << tsh) - 1)) * 2 * SEG * I;   // this segment's rows
             // a segment whose steps reach no tap step runs without the per-step tests
             auto fseg = [&](auto notap_tag) {
                 constexpr bool NOTAP = decltype(notap_tag)::value;
@@ -122,7 +127,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         for (int r = 0; r < 4; ++r) {
                             const int n = n0 + r;
                             if (NOTAP || n < N) {
-                                const Look<R> L = lookup_state<R, AXIS, EX>(y, tab + 2 * (4 * q4 + r) * I,
+                                const Look<R> L = lookup_state<R, AXIS, EX>(y, tt + 2 * (4 * q4 + r) * I,
                                                                             inv_du, a_off, inv_spot, amax, spot);
                                 y = step<R, EX, RT>(y, L.s, z[r], hdt, rdt);
                                 if (!NOTAP && n + 1 == next_tap) {
@@ -188,17 +193,18 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
         for (int sg = n_seg - 1; sg >= 0; --sg) {
             const int na = sg * SEG, nw = min(SEG, N - na);
             const int hi = na / WH;
-            if (hi != hcur || sg != tcur) __syncthreads();
+            if (hi != hcur || (sg >> tsh) != tcur) __syncthreads();
             if (hi != hcur) {
                 fold<R>(a, H, g64, hcur * WH, min(WH, N - hcur * WH), inv_sc);
                 hcur = hi;
             }
-            if (sg != tcur) {
-                stg.issue(a, na, nw);
+            if ((sg >> tsh) != tcur) {
+                stg.issue(a, (sg >> tsh) * a.W, min(a.W, N - (sg >> tsh) * a.W));
                 stg.commit(a, tab);
                 __syncthreads();
-                tcur = sg;
+                tcur = sg >> tsh;
             }
+            const R *tt = tab + (sg & ((1 << tsh) - 1)) * 2 * SEG * I;   // this segment's rows
             if (!wave_on) continue;   // no live path in this wave (the barriers above are the block's)
             // this lane's histogram row of the segment's last step; the sweep steps it back
             // one row per step
@@ -219,7 +225,7 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         for (int r = 0; r < 4; ++r) {
                             const int k = 4 * q4 + r;
                             if (FULL || n0 + r < N) {
-                                const Look<R> L = lookup_state<R, AXIS, EX>(yy, tab + 2 * k * I, inv_du, a_off,
+                                const Look<R> L = lookup_state<R, AXIS, EX>(yy, tt + 2 * k * I, inv_du, a_off,
                                                                             inv_spot, amax, spot);
                                 ys[k] = HS ? L.E : yy;
                                 // the forward's own arithmetic, so the re-simulated states (and
@@ -247,10 +253,10 @@ __global__ void __launch_bounds__(adjoint_max_block(sizeof(R))) k_fused(Args a) 
                         if (NOTAP || na + k < N) {
                             if (HS) {
                                 // d sigma / d y = (d / du) S = (d / du') E
-                                L[r] = lookup_at<R>(ys[k], tab + 2 * k * I, s_inv_du, a_off, amax);
+                                L[r] = lookup_at<R>(ys[k], tt + 2 * k * I, s_inv_du, a_off, amax);
                                 dsd[r] = L[r].in ? L[r].d * s_inv_du * ys[k] : (R)0;
                             } else {
-                                L[r] = lookup_state<R, AXIS, EX>(ys[k], tab + 2 * k * I, inv_du, a_off,
+                                L[r] = lookup_state<R, AXIS, EX>(ys[k], tt + 2 * k * I, inv_du, a_off,
                                                                  inv_spot, amax, spot);
                                 R d = L[r].in ? L[r].d * inv_du : (R)0;
                                 if (AXIS == 0) d *= L[r].S;
@@ -329,7 +335,7 @@ hipError_t LV_FUSED_NAME(LV_FUSED_PREC, LV_FUSED_SEG)(const Args &a, int blocks,
                                                       Ev ev) {
     typedef std::conditional<LV_FUSED_PREC == 64, double, float>::type R;
     constexpr int SEG = LV_FUSED_SEG;
-    const size_t lds = lds_of<R>(FUSED_CKPT, a, block, SEG);
+    const size_t lds = lds_of<R>(FUSED_CKPT, a, block, a.W);
     const bool rt = a.rate_dt != 0.0;
     if (LV_FUSED_PREC == 64 || use_magic(a, LV_FUSED_PREC, block)) {
         if (rt) fused_rt<R, SEG, true, true>(a, blocks, block, lds, st, ev);
