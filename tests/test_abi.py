@@ -228,3 +228,27 @@ def test_device_calls_refuse_host_tensors():
     for k, f in enumerate(calls):
         with pytest.raises(ValueError, match="CUDA tensor"):
             f()
+
+
+def test_planned_checkpoint_table_window_fits_lds():
+    """The checkpointed kernel stages its vol table one, two or four segments at a time,
+    as many as fit beside the smallest histogram window: on the 100 x 50 batch surface
+    and on a 150 x 80 grid near the LDS limit, every block size, copy count, segment
+    length and precision the checker accepts is planned without a 'planner:' refusal."""
+    big = W.Surface(W.Axis(150, W.LOG, 20.0, 400.0), W.Axis(80, W.LIN, 0.0, 2.0),
+                    np.full((150, 80), 0.2))
+    reqs = [_req(surface=W.surface_batch(1).surfaces[0], maturities=[5.0], n_paths=1 << 24, n_steps=260),
+            _req(surface=big, maturities=[2.0], n_paths=(1 << 17) + 5, n_steps=104)]
+    n_ok = 0
+    for req in reqs:
+        for prec, blocks in ((32, (128, 256, 512, 1024)), (64, (128, 256, 512))):
+            for block in blocks:
+                for k in (1, 2, 4):
+                    for seg in (8, 16, 32):
+                        st = lv.check(**req, precision=prec, block=block, copies=k, adjoint="checkpoint",
+                                      ckpt_every=seg)
+                        msg = _lib.load().lv_last_error(None).decode() if st else ""
+                        assert not msg.startswith("planner"), (prec, block, k, seg, msg)
+                        assert st in (_lib.LV_OK, _lib.LV_ERR_UNSUPPORTED), (prec, block, k, seg, st)
+                        n_ok += st == _lib.LV_OK
+    assert n_ok > 60
