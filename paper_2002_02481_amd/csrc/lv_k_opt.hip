@@ -14,7 +14,7 @@
 namespace lvk {
 
 // Steps per table window and histogram window of the per-option sweep.
-constexpr int OW = 8;
+constexpr int OW = 16;
 
 __host__ __device__ inline Lds opt_layout(int rbytes, int I, int J, int wpb, int W, int KO) {
     Lds L{};
